@@ -1,0 +1,86 @@
+"""Posterior predictive mean and variance of the latent M-RA process
+(Sec. 3.4 and Prop. 2), in the paper's notation.
+
+For prediction locations S^P in leaf R = (M, i) with ancestors a_0..a_M = R:
+  U^l   = C_0(S^P, Q_{a_l}) - sum_{k<l} U^k K_{a_k} W^k_{a_l}',  l = 0..M,
+          where Q_{a_M} = S_R and W^k_{a_M} = B^k_R;   L^M = U^M
+  V^P   = C_0(S^P, S^P) - sum_{k=0}^{M-1} U^k K_{a_k} U^k'
+          (the sum's upper limit is printed as l-1 with l undefined; read as M-1)
+  B~^{M,k} = U^k - L^M Sigma_R^{-1} B^k_R                      (eq. bfrecursion, l = M)
+  B~^{l,k} = B~^{l+1,k} - B~^{l+1,l} K~_{a_l} A^{l,k}_{a_l},  l = M-1..1, k < l
+  mean  = sum_{m<M} B~^{m+1,m} K~_{a_m} w^m_{a_m} + L^M Sigma_R^{-1} z_R
+  var   = diag( sum_{m<M} B~^{m+1,m} K~_{a_m} B~^{m+1,m}' + V^P - L^M Sigma_R^{-1} L^M' )
+(eq. prediction: weights eta~_m ~ N(K~ w^m, K~), remainder delta~ with the
+mean and covariance of Prop. 2).  Only the marginal variances are returned.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.linalg import cho_solve
+
+from .covariance import Covariance
+from .geometry import Geometry
+from .mra import loglik
+
+
+def predict(geom: Geometry, z, cov_kind, theta, pred):
+    """(mean, var) of y_M at pred given z (Prop. 2)."""
+    cov = Covariance(cov_kind, theta)
+    _, _, st = loglik(geom, z, cov_kind, theta, grad=False, keep=True)
+    M = geom.M
+    z = np.asarray(z, dtype=np.float64)
+    pred = np.atleast_2d(np.asarray(pred, dtype=np.float64))
+    leafP = geom.leaf_of(pred)
+    mean = np.zeros(pred.shape[0])
+    var = np.zeros(pred.shape[0])
+    for i in np.unique(leafP):
+        ip = np.flatnonzero(leafP == i)
+        SP = pred[ip]
+        anc = geom.ancestors(M, int(i))
+        SR = geom.region_points(M, int(i))
+        zR = z[geom.leaf_obs(int(i))]
+        WR = st.W[(M, int(i))]
+        U = []
+        for l in range(M + 1):
+            Ql = SR if l == M else geom.knots[l][anc[l]]
+            u = cov(SP, Ql)
+            for k in range(l):
+                Wk_al = WR[k] if l == M else st.W[(l, anc[l])][k]
+                u = u - U[k] @ cho_solve(st.Kinv[(k, anc[k])].c, Wk_al.v.T) \
+                    if st.Kinv[(k, anc[k])].c is not None else u
+            U.append(u)
+        LM = U[M]
+        VP = np.diag(cov(SP, SP)).copy()
+        for k in range(M):
+            if st.Kinv[(k, anc[k])].c is None:
+                continue
+            VP -= np.einsum("ij,ji->i", U[k], cho_solve(st.Kinv[(k, anc[k])].c, U[k].T))
+        Sig = st.Sigma[int(i)]
+        if Sig is not None and Sig.c is not None:
+            SiB = [cho_solve(Sig.c, WR[k].v) for k in range(M)]
+            Siz = cho_solve(Sig.c, zR)
+            SiL = cho_solve(Sig.c, LM.T)
+            Bt = {(M, k): U[k] - LM @ SiB[k] for k in range(M)}
+            m_leaf = LM @ Siz
+            v_leaf = VP - np.einsum("ij,ji->i", LM, SiL)
+        else:
+            Bt = {(M, k): U[k] for k in range(M)}
+            m_leaf = np.zeros(SP.shape[0])
+            v_leaf = VP
+        for l in range(M - 1, 0, -1):
+            Kt = st.Ktilde[(l, anc[l])]
+            for k in range(l):
+                Bt[(l, k)] = Bt[(l + 1, k)] - Bt[(l + 1, l)] @ cho_solve(Kt.c, st.A[(l, anc[l])][(l, k)].v) \
+                    if Kt.c is not None else Bt[(l + 1, k)]
+        mu = m_leaf.copy()
+        vv = v_leaf.copy()
+        for m in range(M):
+            Kt = st.Ktilde[(m, anc[m])]
+            if Kt.c is None:
+                continue
+            Bm = Bt[(m + 1, m)]
+            mu += (Bm @ cho_solve(Kt.c, st.omega[(m, anc[m])][m].v)).ravel()
+            vv += np.einsum("ij,ji->i", Bm, cho_solve(Kt.c, Bm.T))
+        mean[ip] = mu
+        var[ip] = vv
+    return mean, var

@@ -1,0 +1,296 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle's recursion against something other than
+itself: the exact Gaussian process (scipy's multivariate normal), closed
+forms stated in the paper, the dense brute-force M-RA covariance assembled
+from the Sec. 2.4 closed form, central finite differences, or exact
+identities.  The paper prints no worked numerical example, so there is no
+table of printed values to pin against.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import block_diag
+from scipy.stats import multivariate_normal
+
+from oracle import dense, mra, predict
+from oracle.covariance import Covariance
+from oracle.geometry import Geometry
+
+COVS = ["matern32", "exponential"]
+
+
+def _data(n, d=2, seed=0):
+    g = np.random.default_rng(seed)
+    return g.random((n, d)), g.standard_normal(n)
+
+
+def _theta(s2=1.3, k=0.2, t2=0.05):
+    return np.array([math.log(s2), math.log(k), math.log(t2)])
+
+
+def _exact_scipy(locs, z, kind, th):
+    cov = Covariance(kind, th)
+    S = cov(locs, locs) + cov.tau2 * np.eye(locs.shape[0])
+    return multivariate_normal(mean=np.zeros(locs.shape[0]), cov=S).logpdf(z)
+
+
+def _fd(f, th, h=1e-5):
+    out = []
+    for p in range(3):
+        e = np.zeros(3)
+        e[p] = h
+        out.append((f(th + e) - f(th - e)) / (2 * h))
+    return np.array(out)
+
+
+# P1: M = 0 is the original process (Sec. 2.4, comparison to the FSA)
+@pytest.mark.parametrize("kind", COVS)
+def test_m0_is_exact_gp(kind):
+    locs, z = _data(150)
+    th = _theta()
+    g = Geometry(locs, 2, 0, 4, 16)
+    ll, gr, _ = mra.loglik(g, z, kind, th, grad=True)
+    ref = _exact_scipy(locs, z, kind, th)
+    assert abs(ll - ref) <= 1e-12 * abs(ref)
+    fd = _fd(lambda t: _exact_scipy(locs, z, kind, t), th)
+    np.testing.assert_allclose(gr, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+# P2: J = 1 puts every pair in the same region at every level, so
+# C_M = C_0 (Sec. 2.4, quality of the covariance approximation)
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("M", [1, 2, 4])
+def test_single_child_partition_is_exact(kind, M):
+    locs, z = _data(120, seed=1)
+    th = _theta()
+    r = 5
+    kg = np.random.default_rng(7)
+    knots = [kg.random((1, r, 2)) for _ in range(M)]   # distinct knots per level
+    g = Geometry(locs, 2, M, 1, r, knots=knots)
+    ll, _, _ = mra.loglik(g, z, kind, th)
+    ref = _exact_scipy(locs, z, kind, th)
+    assert abs(ll - ref) <= 1e-9 * abs(ref)
+    V, _ = dense.data_covariance(g, Covariance(kind, th))
+    cov = Covariance(kind, th)
+    np.testing.assert_allclose(np.diag(V), cov.sigma2 + cov.tau2, rtol=1e-14)
+
+
+# P3: knots equal to the observed locations make the predictive process
+# exact at them (Sec. 2.4, "optimal" basis functions): Q_0 = S, M = 1
+@pytest.mark.parametrize("kind", COVS)
+def test_knots_at_observations_exact(kind):
+    locs, z = _data(64, seed=2)
+    th = _theta(k=0.1, t2=0.1)
+    g = Geometry(locs, 2, 1, 4, 64, knots=[locs[None]])
+    ll, _, _ = mra.loglik(g, z, kind, th)
+    ref = _exact_scipy(locs, z, kind, th)
+    assert abs(ll - ref) <= 1e-9 * abs(ref)
+
+
+# P4: 1-D exponential covariance, knots on the boundaries of the next
+# level's partition: the screening effect is exact, so the M-RA is exact
+# (Sec. 2.5 and the caption of Fig. 1)
+@pytest.mark.parametrize("J", [2, 3])
+@pytest.mark.parametrize("M", [1, 3, 5])
+def test_1d_exponential_boundary_knots_exact(J, M):
+    g0 = np.random.default_rng(3)
+    n = 90
+    locs = g0.random((n, 1))
+    z = g0.standard_normal(n)
+    th = _theta(k=0.3, t2=0.05)
+    r = J - 1
+    knots = []
+    for m in range(M):
+        w = 1.0 / J ** m
+        kk = np.empty((J ** m, r, 1))
+        for i in range(J ** m):
+            a = i * w
+            for k in range(1, J):
+                kk[i, k - 1, 0] = a + (w * k) / J
+        knots.append(kk)
+    g = Geometry(locs, 1, M, J, r, knots=knots)
+    ll, gr, _ = mra.loglik(g, z, "exponential", th, grad=True)
+    ref = _exact_scipy(locs, z, "exponential", th)
+    assert abs(ll - ref) <= 1e-10 * abs(ref)
+    fd = _fd(lambda t: _exact_scipy(locs, z, "exponential", t), th)
+    np.testing.assert_allclose(gr, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+    # exact kriging as well (Fig. 1 (e): the M-RA predictions equal the 0-RA ones)
+    pred = g0.random((25, 1))
+    mu, var = predict.predict(g, z, "exponential", th, pred)
+    mu0, var0 = dense.exact_krige(locs, z, "exponential", th, pred)
+    np.testing.assert_allclose(mu, mu0, rtol=1e-8, atol=1e-9)
+    np.testing.assert_allclose(var, var0, rtol=1e-8, atol=1e-9)
+
+
+def test_1d_default_knots_midpoint_exact():
+    """J = 2, r = 1: the default cell-centred knot is the split point."""
+    g0 = np.random.default_rng(4)
+    locs = g0.random((70, 1))
+    z = g0.standard_normal(70)
+    th = _theta(k=0.15)
+    g = Geometry(locs, 1, 4, 2, 1)
+    ll, _, _ = mra.loglik(g, z, "exponential", th)
+    assert abs(ll - _exact_scipy(locs, z, "exponential", th)) <= 1e-10 * abs(ll)
+
+
+# P5 / P9 / P12: recursion versus the brute-force dense M-RA covariance
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("M,r", [(1, 4), (2, 9), (3, 4), (3, 16)])
+def test_recursion_matches_bruteforce(kind, M, r):
+    locs, z = _data(180, seed=5 + M)
+    th = _theta(s2=0.8, k=0.15, t2=0.02)
+    g = Geometry(locs, 2, M, 4, r)
+    ll, gr, st = mra.loglik(g, z, kind, th, grad=True)
+    lld, grd = dense.mra_loglik_dense(g, z, kind, th, grad=True)
+    assert abs(ll - lld) <= 1e-11 * abs(lld)
+    np.testing.assert_allclose(gr, grd, rtol=1e-9, atol=1e-9 * np.abs(grd).max())
+    # d and u separately (Sec. 3.3): log|Sigma| and z' Sigma^{-1} z
+    V, _ = dense.data_covariance(g, Covariance(kind, th))
+    sign, logdet = np.linalg.slogdet(V)
+    assert sign > 0
+    quad = z @ np.linalg.solve(V, z)
+    assert abs(float(st.d[(0, 0)].v) - logdet) <= 1e-10 * abs(logdet)
+    assert abs(float(st.u[(0, 0)].v) - quad) <= 1e-10 * abs(quad)
+    # central finite differences of the recursion itself
+    fd = _fd(lambda t: mra.loglik(g, z, kind, t)[0], th)
+    np.testing.assert_allclose(gr, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+def test_uneven_and_empty_leaves():
+    """Leaves with 0, 1 and many observations (all observations in one
+    quadrant of the root leave most level-2 leaves empty)."""
+    g0 = np.random.default_rng(9)
+    locs = np.concatenate([g0.random((60, 2)) * 0.5, [[0.9, 0.9]]])
+    z = g0.standard_normal(61)
+    th = _theta()
+    g = Geometry(locs, 2, 2, 4, 4)
+    counts = np.diff(g.offsets)
+    assert (counts == 0).any() and (counts == 1).any()
+    ll, gr, _ = mra.loglik(g, z, "matern32", th, grad=True)
+    lld, grd = dense.mra_loglik_dense(g, z, "matern32", th, grad=True)
+    assert abs(ll - lld) <= 1e-11 * abs(lld)
+    np.testing.assert_allclose(gr, grd, rtol=1e-9)
+
+
+# P6: M = 1 is the full-scale approximation (Sec. 2.4)
+@pytest.mark.parametrize("kind", COVS)
+def test_m1_is_full_scale_approximation(kind):
+    locs, z = _data(160, seed=11)
+    th = _theta()
+    g = Geometry(locs, 2, 1, 4, 9)
+    cov = Covariance(kind, th)
+    Q = g.knots[0][0]
+    CSQ = cov(locs, Q)
+    CQQ = cov(Q, Q)
+    low = CSQ @ np.linalg.solve(CQQ, CSQ.T)
+    Sig = low.copy()
+    for j in range(4):
+        idx = np.flatnonzero(g.leaf == j)
+        Sig[np.ix_(idx, idx)] = cov(locs[idx], locs[idx])
+    Sig += cov.tau2 * np.eye(locs.shape[0])
+    ref = multivariate_normal(mean=np.zeros(len(z)), cov=Sig).logpdf(z)
+    ll, _, _ = mra.loglik(g, z, kind, th)
+    assert abs(ll - ref) <= 1e-11 * abs(ref)
+
+
+# P7: zero knots give the block-independent approximation (Sec. 4.2)
+def test_zero_knots_block_independent():
+    locs, z = _data(150, seed=12)
+    th = _theta()
+    g = Geometry(locs, 2, 1, 4, 0)
+    cov = Covariance("matern32", th)
+    ref = 0.0
+    for j in range(4):
+        idx = np.flatnonzero(g.leaf == j)
+        S = cov(locs[idx], locs[idx]) + cov.tau2 * np.eye(idx.size)
+        ref += multivariate_normal(mean=np.zeros(idx.size), cov=S).logpdf(z[idx])
+    ll, _, _ = mra.loglik(g, z, "matern32", th)
+    assert abs(ll - ref) <= 1e-12 * abs(ref)
+
+
+# P8: Prop. 1 (nonnegative definite covariance) and the Sherman-Morrison-
+# Woodbury identity eq. smw on the dense matrices of a 2-RA
+def test_psd_and_smw():
+    locs, _ = _data(120, seed=13)
+    th = _theta(t2=1e-3)
+    g = Geometry(locs, 2, 2, 4, 9)
+    cov = Covariance("matern32", th)
+    CM, _ = dense.mra_cross(g, cov, locs, g.leaf, locs, g.leaf)
+    ev = np.linalg.eigvalsh(CM)
+    assert ev.min() >= -1e-10 * ev.max()
+    # root (eq. matrices with m = 0): Sigma = B K B' + V with V the
+    # block-diagonal of the level-1 regions' Sigma (var given eta_0)
+    Sig = CM + cov.tau2 * np.eye(len(locs))
+    Q0 = g.knots[0][0]
+    B = cov(locs, Q0)
+    Kinv = cov(Q0, Q0)
+    R = Sig - B @ np.linalg.solve(Kinv, B.T)
+    lvl1 = g.leaf // 4
+    V = np.zeros_like(Sig)
+    for j in range(4):
+        idx = np.flatnonzero(lvl1 == j)
+        V[np.ix_(idx, idx)] = R[np.ix_(idx, idx)]
+    np.testing.assert_allclose(R, V, atol=1e-12)      # off-block part vanishes
+    Vi = np.linalg.inv(V)
+    Kt = np.linalg.inv(Kinv + B.T @ Vi @ B)
+    np.testing.assert_allclose(Vi - Vi @ B @ Kt @ B.T @ Vi, np.linalg.inv(Sig), rtol=1e-7, atol=1e-7)
+
+
+# P10: Prop. 2 versus dense kriging with the brute-force covariance, and
+# M = 0 versus textbook simple kriging
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("M,r", [(0, 4), (1, 9), (2, 4), (3, 4)])
+def test_prediction_matches_dense_kriging(kind, M, r):
+    locs, z = _data(170, seed=20 + M)
+    th = _theta(k=0.25)
+    g = Geometry(locs, 2, M, 4, r)
+    pred = np.random.default_rng(99).random((40, 2))
+    mu, var = predict.predict(g, z, kind, th, pred)
+    if M == 0:
+        mu0, var0 = dense.exact_krige(locs, z, kind, th, pred)
+    else:
+        mu0, var0 = dense.mra_krige_dense(g, z, kind, th, pred)
+    np.testing.assert_allclose(mu, mu0, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(var, var0, rtol=1e-9, atol=1e-10)
+    assert (var > 0).all()
+
+
+# P11: Sigma(c sigma^2, c tau^2) = c Sigma, so
+# dl/dlog sigma^2 + dl/dlog tau^2 = -(n - u)/2 exactly, at any size
+@pytest.mark.parametrize("kind", COVS)
+def test_scale_identity(kind):
+    locs, z = _data(300, seed=30)
+    th = _theta()
+    g = Geometry(locs, 2, 3, 4, 9)
+    _, gr, st = mra.loglik(g, z, kind, th, grad=True)
+    u = float(st.u[(0, 0)].v)
+    assert abs(gr[0] + gr[2] + 0.5 * (len(z) - u)) <= 1e-10 * len(z)
+
+
+def test_dense_gradient_against_fd():
+    """The dense checker's own gradient formula against finite differences."""
+    locs, z = _data(80, seed=31)
+    th = _theta()
+    g = Geometry(locs, 2, 2, 4, 4)
+    _, grd = dense.mra_loglik_dense(g, z, "matern32", th, grad=True)
+    fd = _fd(lambda t: dense.mra_loglik_dense(g, z, "matern32", t)[0], th)
+    np.testing.assert_allclose(grd, fd, rtol=1e-6)
+
+
+def test_covariance_closed_forms():
+    """Matern 1.5 at known distances, and the log-kappa derivative by FD."""
+    th = _theta(s2=2.0, k=0.5, t2=0.1)
+    for kind in COVS:
+        cov = Covariance(kind, th)
+        X = np.array([[0.0, 0.0]])
+        Y = np.array([[0.3, 0.4]])     # distance 0.5 -> h = 1
+        c = cov(X, Y)[0, 0]
+        want = 2.0 * (1 + math.sqrt(3)) * math.exp(-math.sqrt(3)) if kind == "matern32" else 2.0 * math.exp(-1.0)
+        assert abs(c - want) <= 1e-15 * want
+        assert cov(X, X)[0, 0] == 2.0
+        h = 1e-6
+        cp = Covariance(kind, th + np.array([0, h, 0]))(X, Y)[0, 0]
+        cm = Covariance(kind, th - np.array([0, h, 0]))(X, Y)[0, 0]
+        assert abs(cov.tangents(X, Y)[1, 0, 0] - (cp - cm) / (2 * h)) <= 1e-8
