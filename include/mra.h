@@ -1,0 +1,168 @@
+/*
+ * mra.h - C ABI of the MI355X multi-resolution approximation (M-RA) library.
+ *
+ * Computes, for the M-RA of a Gaussian process (Katzfuss, "A multi-resolution
+ * approximation for massive spatial datasets", JASA 2017, arXiv 1507.04789):
+ *   - the log-likelihood of data z observed with measurement error
+ *     (Sec. 3.3 with the leaf covariance of Sec. 4.2),
+ *   - its gradient with respect to theta = (log sigma^2, log kappa, log tau^2),
+ *   - the posterior predictive mean and variance of the latent process
+ *     (Sec. 3.4, Prop. 2),
+ * with all floating point in FP64.
+ *
+ * Model.  C_0(s, s') = sigma^2 rho(||s - s'|| / kappa), rho the Matern
+ * correlation with smoothness 1.5 (eq. mat15) or the exponential
+ * correlation exp(-h); data z = y_M(S) + eps, eps ~ N(0, tau^2 I).
+ * The domain box is split recursively into J regions per level, levels
+ * 0..M (Sec. 2.2); every region below level M holds r knots, the knots of
+ * level M are the observations (Sec. 2.2).
+ *
+ * Memory.  The library never allocates device memory.  mra_requirements
+ * reports the byte sizes of a geometry arena and a work arena; the caller
+ * allocates them (e.g. as torch tensors) and hands them over in mra_bind.
+ * Pointers named d_* are device pointers owned by the caller; h_* are host
+ * pointers owned by the caller and only read during the call.
+ *
+ * Streams.  Every call that takes a stream enqueues its work on that HIP
+ * stream (hipStream_t passed as void*; NULL is the null stream) and returns
+ * without waiting unless the plan was built with MRA_SYNC, in which case it
+ * synchronises the stream and reports Cholesky breakdowns as MRA_ENOTPD.
+ *
+ * Ordering.  y, mean and var are in the caller's original order of the
+ * locations; the plan permutes internally.
+ *
+ * Threading.  A plan is not thread-safe; calls on one plan must not overlap.
+ */
+#ifndef MRA_H
+#define MRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mra_plan_s* mra_plan_t;
+
+typedef enum {
+  MRA_OK = 0,
+  MRA_EINVAL = -1,   /* bad configuration, argument, or location outside the box */
+  MRA_ENOTPD = -2,   /* a Cholesky factor broke down (matrix not positive definite) */
+  MRA_ENOMEM = -3,   /* host allocation failed or bound arenas too small */
+  MRA_EHIP = -4,     /* a HIP runtime call failed */
+  MRA_ESTATE = -5    /* call order violated (e.g. loglik before bind) */
+} mra_status;
+
+typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
+
+/* flags */
+#define MRA_SYNC   1u   /* synchronise after each call and check factor status */
+#define MRA_PLAIN  2u   /* one kernel launch per region / task (comparison form) */
+#define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
+
+typedef struct {
+  int32_t d;            /* spatial dimension: 1 or 2 */
+  int32_t M;            /* number of partition levels; M = 0 is the exact GP (Sec. 2.4) */
+  int32_t J;            /* children per region: d = 2: 1 or 4 (quadrants); d = 1: 1..8 */
+  int32_t r;            /* knots per region below level M, 1..64; d = 2 default knots need a square r */
+  double lo[2], hi[2];  /* domain box (only the first d entries are read) */
+  int32_t cov;          /* mra_cov */
+  int32_t max_theta;    /* largest parameter batch a call may pass (>= 1) */
+  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH */
+} mra_config;
+
+typedef struct {
+  int64_t n;            /* observations */
+  int64_t n_pred;       /* prediction locations */
+  int64_t n_rows_pad;   /* observation rows after padding every leaf to a multiple of 64 */
+  int64_t n_leaves;     /* J^M */
+  int64_t n_regions;    /* sum_m J^m */
+  int64_t max_leaf;     /* largest leaf count */
+  double flops_loglik;  /* algorithmic FP64 flops of one log-likelihood */
+  double flops_grad;    /* algorithmic FP64 flops of one log-likelihood + gradient */
+  double flops_predict; /* algorithmic FP64 flops of one prediction pass */
+} mra_info;
+
+/*
+ * Build a plan: partition the box, assign observations and prediction
+ * locations to leaves, place knots (Sec. 2.2, 2.5).  Host only; touches no
+ * GPU.  h_locs: n x d row-major; h_pred: n_pred x d (may be NULL with
+ * n_pred = 0); h_knots: optional explicit knots, (sum_{m<M} J^m) x r x d in
+ * level-major, region-major order, NULL for the default cell-centred grid.
+ * Splits: d = 2, J = 4 at the midpoint 0.5*(a+b) of each side, child
+ * 2*[y >= ymid] + [x >= xmid]; d = 1 at a + ((b-a)*j)/J.  Returns
+ * MRA_EINVAL for out-of-box or non-finite locations or unsupported
+ * settings, MRA_ENOMEM if a host allocation fails.  *out is owned by the
+ * caller and released with mra_destroy.
+ */
+mra_status mra_build(const mra_config* cfg, const double* h_locs, int64_t n,
+                     const double* h_pred, int64_t n_pred, const double* h_knots,
+                     mra_plan_t* out);
+
+/* Byte sizes of the geometry arena (theta-independent) and of the work
+ * arena (max_theta parameter vectors, all passes).  Host only. */
+mra_status mra_requirements(mra_plan_t plan, size_t* geom_bytes, size_t* work_bytes);
+
+/* Sizes and the algorithmic flop counts of the plan.  Host only. */
+mra_status mra_get_info(mra_plan_t plan, mra_info* info);
+
+/* Geometry as built, for checking against an independent implementation.
+ * Any pointer may be NULL.  h_perm[n]: original index of the k-th
+ * observation in leaf order; h_leaf_offsets[J^M + 1]: CSR offsets of the
+ * leaves in that order; h_knots: (sum_{m<M} J^m) x r x d.  Host only. */
+mra_status mra_get_geometry(mra_plan_t plan, int64_t* h_perm, int64_t* h_leaf_offsets,
+                            double* h_knots);
+
+/* Bind caller-owned device arenas (at least the required sizes, 256-byte
+ * aligned) and upload the geometry on `stream`.  Must precede every
+ * compute call; may be called again to move the plan to new arenas. */
+mra_status mra_bind(mra_plan_t plan, void* d_geom, size_t geom_bytes, void* d_work,
+                    size_t work_bytes, void* stream);
+
+/*
+ * Log-likelihood (Sec. 3.3): loglik = -1/2 (d + u) - (n/2) log(2 pi), with
+ * d = log|Sigma|, u = z' Sigma^{-1} z for the M-RA data covariance
+ * Sigma(theta) (eq. matrices with m = 0, leaf covariance with tau^2 I).
+ * d_y[n] data (original order); d_theta[n_theta][3] = (log sigma^2,
+ * log kappa, log tau^2); d_loglik[n_theta] output.  1 <= n_theta <=
+ * max_theta.  An entry whose factorisation breaks down is NaN; with
+ * MRA_SYNC the call then returns MRA_ENOTPD and mra_last_failure names it.
+ */
+mra_status mra_loglik(mra_plan_t plan, const double* d_y, const double* d_theta,
+                      int32_t n_theta, double* d_loglik, void* stream);
+
+/*
+ * Log-likelihood and its gradient d_grad[n_theta][3] =
+ * d loglik / d (log sigma^2, log kappa, log tau^2), by a hand-written
+ * reverse pass over the prior recursion (eq. priorw), the leaf quantities
+ * and the posterior recursion (eq. posterior, helpquantities).
+ */
+mra_status mra_loglik_grad(mra_plan_t plan, const double* d_y, const double* d_theta,
+                           int32_t n_theta, double* d_loglik, double* d_grad, void* stream);
+
+/*
+ * Posterior predictive mean and variance of the latent process y_M at the
+ * plan's prediction locations (Prop. 2, marginal variances), for one
+ * parameter vector d_theta[3].  d_mean[n_pred], d_var[n_pred] in the
+ * original order of h_pred.
+ */
+mra_status mra_predict(mra_plan_t plan, const double* d_y, const double* d_theta,
+                       double* d_mean, double* d_var, void* stream);
+
+/* After a call that returned MRA_ENOTPD (or after synchronising a call
+ * made without MRA_SYNC): the first failing (theta index, level, region).
+ * Synchronises `stream`.  Returns MRA_OK with theta_idx = -1 if none. */
+mra_status mra_last_failure(mra_plan_t plan, int32_t* theta_idx, int32_t* level,
+                            int64_t* region, void* stream);
+
+const char* mra_status_string(mra_status s);
+
+/* Release the plan (and any captured graphs).  Does not free the arenas. */
+void mra_destroy(mra_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRA_H */

@@ -1,0 +1,208 @@
+"""MI355X-native multi-resolution approximation (M-RA) of Gaussian processes.
+
+FP64 log-likelihood, its gradient in (log sigma^2, log kappa, log tau^2) and
+kriging for the M-RA of Katzfuss (JASA 2017, arXiv 1507.04789), computed by
+hand-written HIP kernels for gfx950 behind the C ABI of include/mra.h.  This
+module only marshals arguments: device memory and streams come from torch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import MRA_GRAPH, MRA_PLAIN, MRA_SYNC, MRAError
+
+__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH"]
+
+_COV = {"exponential": _lib.MRA_COV_EXPONENTIAL, "matern32": _lib.MRA_COV_MATERN32}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A built M-RA plan.
+
+    locs: (n, d) float64 observation locations; pred: optional (n_pred, d)
+    prediction locations; knots: optional explicit knots, a list over levels
+    m < M of arrays (J^m, r, d).  The geometry is built on the host; device
+    arenas are allocated with torch and bound on first use (or bind()).
+    """
+
+    def __init__(self, locs, *, M: int, J: int, r: int, cov: str, d: int | None = None,
+                 lo=None, hi=None, pred=None, knots=None, max_theta: int = 1,
+                 flags: int = MRA_SYNC):
+        L = _lib.lib()
+        locs = np.ascontiguousarray(np.asarray(locs, dtype=np.float64))
+        if locs.ndim == 1:
+            locs = locs[:, None]
+        d = locs.shape[1] if d is None else d
+        self.n, self.d, self.M, self.J, self.r = locs.shape[0], d, M, J, r
+        cfg = _lib.Config()
+        cfg.d, cfg.M, cfg.J, cfg.r = d, M, J, r
+        lo = [0.0] * d if lo is None else list(lo)
+        hi = [1.0] * d if hi is None else list(hi)
+        for a in range(2):
+            cfg.lo[a] = lo[a] if a < d else 0.0
+            cfg.hi[a] = hi[a] if a < d else 0.0
+        cfg.cov = _COV[cov]
+        cfg.max_theta = max_theta
+        cfg.flags = flags
+        self.cfg = cfg
+        self.cov = cov
+        self.max_theta = max_theta
+        self.flags = flags
+        if pred is not None:
+            pred = np.ascontiguousarray(np.asarray(pred, dtype=np.float64).reshape(-1, d))
+        self.n_pred = 0 if pred is None else pred.shape[0]
+        kn = None
+        if knots is not None:
+            kn = np.ascontiguousarray(np.concatenate([np.asarray(k, dtype=np.float64).reshape(-1) for k in knots]))
+        h = C.c_void_p()
+        s = L.mra_build(C.byref(cfg), locs.ctypes.data, self.n,
+                        None if pred is None else pred.ctypes.data, self.n_pred,
+                        None if kn is None else kn.ctypes.data, C.byref(h))
+        _lib.check(s, "mra_build")
+        self._h = h
+        g, w = C.c_size_t(), C.c_size_t()
+        _lib.check(L.mra_requirements(h, C.byref(g), C.byref(w)), "mra_requirements")
+        self.geom_bytes, self.work_bytes = g.value, w.value
+        info = _lib.Info()
+        _lib.check(L.mra_get_info(h, C.byref(info)), "mra_get_info")
+        self.info = {f: getattr(info, f) for f, _ in _lib.Info._fields_}
+        self._geom = self._work = None
+        self.device = None
+
+    # -- host-side queries --------------------------------------------------
+    def geometry(self):
+        """(perm, leaf_offsets, knots) as built by the library."""
+        L = _lib.lib()
+        perm = np.empty(self.n, dtype=np.int64)
+        off = np.empty(self.J ** self.M + 1, dtype=np.int64)
+        nint = sum(self.J ** m for m in range(self.M))
+        kn = np.empty(max(nint * self.r * self.d, 1), dtype=np.float64)
+        _lib.check(L.mra_get_geometry(self._h, perm.ctypes.data, off.ctypes.data, kn.ctypes.data), "mra_get_geometry")
+        return perm, off, kn[:nint * self.r * self.d].reshape(nint, self.r, self.d)
+
+    # -- device ---------------------------------------------------------------
+    def bind(self, device="cuda"):
+        torch = _torch()
+        dev = torch.device(device)
+        if dev.type != "cuda":
+            raise RuntimeError("the M-RA library runs on a GPU device only")
+        self._geom = torch.empty(self.geom_bytes + 256, dtype=torch.uint8, device=dev)
+        self._work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=dev)
+        gp = (self._geom.data_ptr() + 255) // 256 * 256
+        wp = (self._work.data_ptr() + 255) // 256 * 256
+        st = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(_lib.lib().mra_bind(self._h, gp, self.geom_bytes, wp, self.work_bytes, st), "mra_bind")
+        self.device = dev
+        return self
+
+    def _ensure(self, t):
+        if self.device is None:
+            self.bind(t.device if t.is_cuda else "cuda")
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _prep(self, y, theta):
+        torch = _torch()
+        y = torch.as_tensor(y, dtype=torch.float64)
+        theta = torch.as_tensor(theta, dtype=torch.float64)
+        if not y.is_cuda:
+            y = y.to("cuda")
+        self._ensure(y)
+        y = y.to(self.device).contiguous()
+        theta = theta.to(self.device).reshape(-1, 3).contiguous()
+        if y.numel() != self.n:
+            raise ValueError("y has %d entries, plan has %d locations" % (y.numel(), self.n))
+        if theta.shape[0] > self.max_theta:
+            raise ValueError("%d parameter vectors exceed max_theta=%d" % (theta.shape[0], self.max_theta))
+        return y, theta
+
+    def _fail(self, s, where):
+        if s == _lib.MRA_ENOTPD:
+            th, lv, rg = C.c_int32(), C.c_int32(), C.c_int64()
+            _lib.lib().mra_last_failure(self._h, C.byref(th), C.byref(lv), C.byref(rg), self._stream())
+            raise MRAError(s, where, ": theta %d, level %d, region %d" % (th.value, lv.value, rg.value))
+        _lib.check(s, where)
+
+    def loglik(self, y, theta):
+        """Log-likelihood for each row of theta (n_theta x 3)."""
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        out = torch.empty(theta.shape[0], dtype=torch.float64, device=self.device)
+        s = _lib.lib().mra_loglik(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
+                                  self._stream())
+        self._fail(s, "mra_loglik")
+        return out
+
+    def loglik_grad(self, y, theta):
+        """(loglik [n_theta], grad [n_theta, 3])."""
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        out = torch.empty(theta.shape[0], dtype=torch.float64, device=self.device)
+        g = torch.empty(theta.shape[0], 3, dtype=torch.float64, device=self.device)
+        s = _lib.lib().mra_loglik_grad(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
+                                       g.data_ptr(), self._stream())
+        self._fail(s, "mra_loglik_grad")
+        return out, g
+
+    def predict(self, y, theta):
+        """Posterior predictive (mean, var) of the latent process at the
+        plan's prediction locations, for one parameter vector."""
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        mean = torch.empty(self.n_pred, dtype=torch.float64, device=self.device)
+        var = torch.empty(self.n_pred, dtype=torch.float64, device=self.device)
+        s = _lib.lib().mra_predict(self._h, y.data_ptr(), theta[:1].data_ptr(), mean.data_ptr(), var.data_ptr(),
+                                   self._stream())
+        self._fail(s, "mra_predict")
+        return mean, var
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.mra_destroy(h)
+            self._h = None
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class MRALogLik(torch.autograd.Function):
+        """loglik(theta) with the library's reverse-pass gradient.
+
+        forward(theta [n_theta, 3], plan, y) -> loglik [n_theta]; the
+        gradient with respect to y is not provided."""
+
+        @staticmethod
+        def forward(ctx, theta, plan, y):
+            ll, g = plan.loglik_grad(y, theta.detach())
+            ctx.save_for_backward(g)
+            return ll
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return gout[:, None] * g, None, None
+
+    return MRALogLik
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, k):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_autograd()
+        return getattr(_Lazy._cls, k)
+
+
+MRALogLik = _Lazy()

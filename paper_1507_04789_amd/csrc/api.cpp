@@ -1,0 +1,222 @@
+// C ABI of the M-RA library (declared in include/mra.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace mra {
+
+hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st);
+hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st);
+
+namespace {
+
+mra_status check_hip(hipError_t e) { return e == hipSuccess ? MRA_OK : MRA_EHIP; }
+
+// after a synchronised call: find the first parameter vector whose
+// factorisations broke down
+mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
+  if (hipStreamSynchronize(st) != hipSuccess) return MRA_EHIP;
+  H->fail_theta = -1;
+  H->fail_level = -1;
+  H->fail_region = -1;
+  for (int th = 0; th < nth; ++th) {
+    int64_t code = 0;
+    const double* src = H->dp.work + (int64_t)th * H->dp.theta_stride + H->dp.off_status;
+    if (hipMemcpy(&code, src, sizeof(code), hipMemcpyDeviceToHost) != hipSuccess) return MRA_EHIP;
+    if (code != 0) {
+      H->fail_theta = th;
+      code -= 1;
+      H->fail_level = (int32_t)(code >> 40);
+      H->fail_region = code & ((1ll << 40) - 1);
+      return MRA_ENOTPD;
+    }
+  }
+  return MRA_OK;
+}
+
+mra_status check_call(const mra_plan_s* H, int nth) {
+  if (!H) return MRA_EINVAL;
+  if (!H->bound) return MRA_ESTATE;
+  if (nth < 1 || nth > H->cfg.max_theta) return MRA_EINVAL;
+  return MRA_OK;
+}
+
+}  // namespace
+}  // namespace mra
+
+using namespace mra;
+
+extern "C" {
+
+mra_status mra_build(const mra_config* cfg, const double* h_locs, int64_t n, const double* h_pred, int64_t n_pred,
+                     const double* h_knots, mra_plan_t* out) {
+  if (!out) return MRA_EINVAL;
+  *out = nullptr;
+  mra_plan_s* P = new (std::nothrow) mra_plan_s();
+  if (!P) return MRA_ENOMEM;
+  mra_status s;
+  try {
+    s = build_plan(cfg, h_locs, n, h_pred, n_pred, h_knots, P);
+  } catch (const std::bad_alloc&) {
+    s = MRA_ENOMEM;
+  }
+  if (s != MRA_OK) {
+    delete P;
+    return s;
+  }
+  *out = P;
+  return MRA_OK;
+}
+
+mra_status mra_requirements(mra_plan_t P, size_t* geom_bytes, size_t* work_bytes) {
+  if (!P) return MRA_EINVAL;
+  if (geom_bytes) *geom_bytes = P->lay.geom_bytes;
+  if (work_bytes) *work_bytes = (size_t)P->lay.theta_stride * 8 * (size_t)P->cfg.max_theta;
+  return MRA_OK;
+}
+
+mra_status mra_get_info(mra_plan_t P, mra_info* info) {
+  if (!P || !info) return MRA_EINVAL;
+  info->n = P->n;
+  info->n_pred = P->n_pred;
+  info->n_rows_pad = P->npad;
+  info->n_leaves = P->nreg[P->M];
+  info->n_regions = P->reg_base[P->M] + P->nreg[P->M];
+  info->max_leaf = P->max_leaf;
+  info->flops_loglik = P->flops_loglik;
+  info->flops_grad = P->flops_grad;
+  info->flops_predict = P->flops_predict;
+  return MRA_OK;
+}
+
+mra_status mra_get_geometry(mra_plan_t P, int64_t* h_perm, int64_t* h_leaf_offsets, double* h_knots) {
+  if (!P) return MRA_EINVAL;
+  if (h_perm) std::memcpy(h_perm, P->perm.data(), P->perm.size() * sizeof(int64_t));
+  if (h_leaf_offsets) std::memcpy(h_leaf_offsets, P->leaf_off.data(), P->leaf_off.size() * sizeof(int64_t));
+  if (h_knots && !P->knots.empty()) std::memcpy(h_knots, P->knots.data(), P->knots.size() * sizeof(double));
+  return MRA_OK;
+}
+
+mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work, size_t work_bytes, void* stream) {
+  if (!P || !d_geom || !d_work) return MRA_EINVAL;
+  if (((uintptr_t)d_geom & 255) || ((uintptr_t)d_work & 255)) return MRA_EINVAL;
+  size_t need_g, need_w;
+  mra_requirements(P, &need_g, &need_w);
+  if (geom_bytes < need_g || work_bytes < need_w) return MRA_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* g = (char*)d_geom;
+  const Layout& L = P->lay;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> bool {
+    if (bytes == 0) return true;
+    return hipMemcpyAsync(g + off, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = up(L.g_knot, P->knot_xy.data(), P->knot_xy.size() * 8) && up(L.g_obs, P->obs_xy.data(), P->obs_xy.size() * 8) &&
+            up(L.g_gidx, P->obs_gidx.data(), P->obs_gidx.size() * 8) &&
+            up(L.g_leafn, P->leaf_n.data(), P->leaf_n.size() * 4) &&
+            up(L.g_poff, P->leaf_poff.data(), P->leaf_poff.size() * 8) &&
+            up(L.g_soff, P->leaf_soff.data(), P->leaf_soff.size() * 8) &&
+            up(L.g_doff, P->leaf_doff.data(), P->leaf_doff.size() * 8) &&
+            up(L.g_rowt, P->row_tasks.data(), P->row_tasks.size() * 4) &&
+            up(L.g_sigt, P->sig_tasks.data(), P->sig_tasks.size() * 4) &&
+            up(L.g_fact, P->fac_tasks.data(), P->fac_tasks.size() * 4) &&
+            up(L.g_trst, P->trsm_tasks.data(), P->trsm_tasks.size() * 4) &&
+            up(L.g_pxy, P->pred_xy.data(), P->pred_xy.size() * 8) &&
+            up(L.g_pgidx, P->pred_gidx.data(), P->pred_gidx.size() * 8) &&
+            up(L.g_pt, P->pred_tasks.data(), P->pred_tasks.size() * 4) &&
+            up(L.g_pleafn, P->pleaf_n.data(), P->pleaf_n.size() * 4);
+  if (!ok || hipStreamSynchronize(st) != hipSuccess) return MRA_EHIP;
+  DevPlan& D = P->dp;
+  D.knot_xy = (const double*)(g + L.g_knot);
+  D.obs_xy = (const double*)(g + L.g_obs);
+  D.obs_gidx = (const int64_t*)(g + L.g_gidx);
+  D.leaf_n = (const int32_t*)(g + L.g_leafn);
+  D.leaf_poff = (const int64_t*)(g + L.g_poff);
+  D.leaf_soff = (const int64_t*)(g + L.g_soff);
+  D.leaf_doff = (const int64_t*)(g + L.g_doff);
+  D.row_tasks = (const int32_t*)(g + L.g_rowt);
+  D.sig_tasks = (const int32_t*)(g + L.g_sigt);
+  D.fac_tasks = (const int32_t*)(g + L.g_fact);
+  D.trsm_tasks = (const int32_t*)(g + L.g_trst);
+  D.pred_xy = (const double*)(g + L.g_pxy);
+  D.pred_gidx = (const int64_t*)(g + L.g_pgidx);
+  D.pred_tasks = (const int32_t*)(g + L.g_pt);
+  D.pleaf_n = (const int32_t*)(g + L.g_pleafn);
+  D.work = (double*)d_work;
+  P->d_geom = d_geom;
+  P->d_work = d_work;
+  P->bound = true;
+  return MRA_OK;
+}
+
+mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
+                      void* stream) {
+  mra_status s = check_call(P, n_theta);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_theta || !d_loglik) return MRA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
+  return MRA_OK;
+}
+
+mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
+                           double* d_grad, void* stream) {
+  mra_status s = check_call(P, n_theta);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
+  if (s != MRA_OK) return s;
+  s = check_hip(launch_grad(*P, d_theta, n_theta, d_grad, st));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
+  return MRA_OK;
+}
+
+mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_var,
+                       void* stream) {
+  mra_status s = check_call(P, 1);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_theta || !d_mean || !d_var) return MRA_EINVAL;
+  if (P->n_pred == 0) return MRA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  s = check_hip(launch_forward(*P, d_y, d_theta, 1, nullptr, st));
+  if (s != MRA_OK) return s;
+  s = check_hip(launch_predict(*P, d_theta, d_mean, d_var, st));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
+  return MRA_OK;
+}
+
+mra_status mra_last_failure(mra_plan_t P, int32_t* theta_idx, int32_t* level, int64_t* region, void* stream) {
+  if (!P) return MRA_EINVAL;
+  if (!(P->cfg.flags & MRA_SYNC) && P->bound) {
+    mra_status s = collect_failures(P, P->cfg.max_theta, (hipStream_t)stream);
+    if (s == MRA_EHIP) return s;
+  }
+  if (theta_idx) *theta_idx = P->fail_theta;
+  if (level) *level = P->fail_level;
+  if (region) *region = P->fail_region;
+  return MRA_OK;
+}
+
+const char* mra_status_string(mra_status s) {
+  switch (s) {
+    case MRA_OK: return "ok";
+    case MRA_EINVAL: return "invalid argument or configuration";
+    case MRA_ENOTPD: return "Cholesky factor broke down (matrix not positive definite)";
+    case MRA_ENOMEM: return "out of memory or arena too small";
+    case MRA_EHIP: return "HIP runtime error";
+    case MRA_ESTATE: return "plan not bound";
+  }
+  return "unknown status";
+}
+
+void mra_destroy(mra_plan_t P) { delete P; }
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Device-visible description of a bound M-RA plan: pointers into the
+// caller's geometry and work arenas plus the level tables.  Passed to every
+// kernel by value.
+#pragma once
+#include <stdint.h>
+
+namespace mra {
+
+constexpr int T = 64;                 // tile edge: knots per region are padded to T
+constexpr int64_t TT = (int64_t)T * T;
+constexpr int MAXL = 12;              // levels 0..MAXL-1 supported (M <= 11)
+
+// Failure code written to the per-theta status word: 1 + level * 2^40 + region
+__host__ __device__ inline int64_t fail_code(int level, int64_t region) {
+  return 1 + ((int64_t)level << 40) + region;
+}
+
+struct DevPlan {
+  int32_t d, M, J, r, cov;
+  int64_t n, npad, n_leaves, ppad, n_pred;
+
+  // geometry arena
+  const double* knot_xy;     // [n_internal][T][2], padded knots have zero coordinates
+  const double* obs_xy;      // [npad][2] leaf-sorted, padded rows zero
+  const int64_t* obs_gidx;   // [npad] original index of the row, -1 for padding
+  const int32_t* leaf_n;     // [n_leaves] observations per leaf
+  const int64_t* leaf_poff;  // [n_leaves + 1] first padded row of each leaf
+  const int64_t* leaf_soff;  // [n_leaves] first Sigma tile of each leaf (nb*nb tiles)
+  const int64_t* leaf_doff;  // [n_leaves] first diagonal-inverse tile (nb tiles)
+  const int32_t* row_tasks;  // [n_row_tasks][2] (leaf, first padded row)
+  const int32_t* sig_tasks;  // [n_sig_tasks][3] (leaf, bi, bj), bi >= bj
+  const int32_t* fac_tasks;  // [n_fac_tasks] nonempty leaves, largest first
+  const int32_t* trsm_tasks; // [n_trsm_tasks][2] (leaf, column plane 0..M)
+  const double* pred_xy;     // [ppad][2]
+  const int64_t* pred_gidx;  // [ppad]
+  const int32_t* pred_tasks; // [n_pred_tasks][2] (leaf, first padded prediction row)
+  const int32_t* pleaf_n;    // [n_leaves]
+
+  // level tables
+  int64_t nreg[MAXL];        // J^m
+  int64_t reg_base[MAXL];    // index of the first region of level m among internal regions
+  int64_t prior_off[MAXL];   // offset (doubles) of level m prior storage in a theta slice
+  int64_t post_off[MAXL];    // offset of level m posterior storage
+  int64_t post_stride[MAXL]; // doubles per region of level m posterior storage
+  int64_t grad_off[MAXL];    // offset of level m reverse-pass storage
+  int64_t grad_stride[MAXL];
+
+  // work arena, one slice of theta_stride doubles per parameter vector
+  double* work;
+  int64_t theta_stride;
+  int64_t off_wobs;    // (M+1) planes of [npad][T]; plane M holds z in column 0
+  int64_t plane;       // npad * T
+  int64_t off_sig;     // Sigma / its Cholesky factor, tiles
+  int64_t off_dinv;    // inverses of the diagonal tiles of the leaf factors
+  int64_t off_y;       // (M+1) planes: Y = L_Sigma^{-1} [W^ | z]
+  int64_t off_leafd;   // [n_leaves] log|Sigma_R|
+  int64_t off_status;  // 1 int64 status word
+  int64_t off_scal;    // scratch scalars (loglik, partial gradient sums)
+  // reverse pass
+  int64_t off_v;       // (M+1) planes: V = L_Sigma^{-T} Y
+  int64_t off_q;       // (M+1) planes: Q = V Fbar
+  int64_t off_sbar;    // Sigma-bar tiles (same layout as off_sig)
+  int64_t off_wbar;    // M planes: cotangent of the leaf rows of W^ (then W-bar)
+  int64_t off_gpart;   // gradient partial sums, [n_gpart][4]
+  int64_t n_gpart;
+  // prediction
+  int64_t off_pw;      // M planes [ppad][T] of U^ rows, then B~ rows
+  int64_t off_pl;      // [ppad][T * nbmax] scratch for L^M rows
+};
+
+}  // namespace mra

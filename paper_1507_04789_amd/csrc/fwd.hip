@@ -1,0 +1,429 @@
+// Forward M-RA kernels: prior quantities (eq. priorw), leaf quantities
+// (eq. helpquantities at m = M), posterior recursion (eq. posterior,
+// mainquantities, helpquantities) and the log-likelihood (Sec. 3.3).
+//
+// Whitened form.  With K_a^{-1} = W^{level(a)}_a = L_a L_a', the blocks
+// W^^k_R = W^k_R L_{a_k}^{-T} turn eq. priorw into a block Cholesky along
+// each chain of regions:
+//   W^l_R = C_0(Q_R, Q_{a_l}) - sum_{k<l} W^^k_R W^^k_{a_l}',
+//   W^^l_R = W^l_R L_{a_l}^{-T},   L_R = chol(W^m_R).
+// The weights xi_a = L_a' eta_a are then N(0, I), the leaf basis rows are
+// W^^k_R, and the posterior precision of xi_R given the finer levels is
+// I + A^{m,m}_R (the whitened K~^{-1}).  log|K~^{-1}| - log|K^{-1}| =
+// log|I + A^{m,m}|, so the d and u recursions of Sec. 3.3 keep their form.
+#include "cov.hpp"
+#include "plan.hpp"
+#include "launch.hpp"
+
+namespace mra {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double* slice(const DevPlan& P, int th) { return P.work + (int64_t)th * P.theta_stride; }
+
+__device__ __forceinline__ double* prior_reg(const DevPlan& P, double* S, int m, int64_t i) {
+  return S + P.prior_off[m] + i * (int64_t)(m + 2) * TT;
+}
+__device__ __forceinline__ const double* knots_of(const DevPlan& P, int m, int64_t i) {
+  return P.knot_xy + (P.reg_base[m] + i) * (2 * T);
+}
+__device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, int l) {
+  for (int q = m; q > l; --q) i /= P.J;
+  return i;
+}
+__device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
+__device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
+  k = 0;
+  while ((k + 1) * (k + 2) / 2 <= kl) ++k;
+  l = kl - k * (k + 1) / 2;
+}
+
+// posterior storage of region (m, i)
+struct Post {
+  double* base;
+  int m;
+  __device__ double* A(int k, int l) const { return base + (int64_t)kl_index(k, l) * TT; }
+  __device__ double* omega(int k) const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + k * T; }
+  __device__ double* Lt() const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + (m + 1) * T; }
+  __device__ double* Lti() const { return Lt() + TT; }
+  __device__ double* Z(int l) const { return Lt() + 2 * TT + (int64_t)l * TT; }
+  __device__ double* zw() const { return Lt() + 2 * TT + (int64_t)m * TT; }
+  __device__ double* d() const { return zw() + T; }
+  __device__ double* u() const { return zw() + T + 1; }
+};
+__device__ __forceinline__ Post post_of(const DevPlan& P, double* S, int m, int64_t i) {
+  Post p;
+  p.base = S + P.post_off[m] + i * P.post_stride[m];
+  p.m = m;
+  return p;
+}
+
+__device__ __forceinline__ void record_failure(const DevPlan& P, double* S, int level, int64_t region) {
+  atomicCAS((unsigned long long*)(S + P.off_status), 0ull, (unsigned long long)fail_code(level, region));
+}
+
+// Row sweep of eq. priorw for 64 rows (points X, nx valid) of a region at
+// level `lev` with index `idx`: writes W^^l (l < lev) to rows + l*bstride.
+__device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
+                          int64_t bstride, int lev, int64_t idx, double* lds) {
+  Acc acc;
+  for (int l = 0; l < lev; ++l) {
+    const int64_t al = ancestor(P, lev, idx, l);
+    const double* Pa = prior_reg(P, S, l, al);
+    acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
+    for (int k = 0; k < l; ++k) gemm<Op::N, Op::T>(acc, rows + k * bstride, T, Pa + k * TT, T, T, -1.0, lds);
+    double* out = rows + l * bstride;
+    acc_store(acc, out, T);
+    __syncthreads();
+    acc_zero(acc);
+    gemm<Op::N, Op::T>(acc, out, T, Pa + (l + 1) * TT, T, T, 1.0, lds);   // W^l L_{a_l}^{-T}
+    acc_store(acc, out, T);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+// zero the per-theta status word and leaf log-determinants
+__global__ void k_init(DevPlan P) {
+  double* S = slice(P, blockIdx.y);
+  for (int64_t q = blockIdx.x * (int64_t)NT + threadIdx.x; q < P.n_leaves; q += (int64_t)gridDim.x * NT)
+    S[P.off_leafd + q] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x < 4) S[P.off_status + threadIdx.x] = 0.0;
+}
+
+// plane M of the leaf rows: z in column 0 (leaf order, padded), zero elsewhere
+__global__ void k_gather(DevPlan P, const double* y) {
+  double* S = slice(P, blockIdx.y);
+  double* zp = S + P.off_wobs + (int64_t)P.M * P.plane;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < P.plane; e += (int64_t)gridDim.x * NT) {
+    int64_t p = e >> 6;
+    int col = (int)(e & 63);
+    int64_t g = P.obs_gidx[p];
+    zp[e] = (col == 0 && g >= 0) ? y[g] : 0.0;
+  }
+}
+
+// prior level m < M: one workgroup per region
+__global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, int m, int64_t i0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int64_t i = i0 + blockIdx.x;
+  double* S = slice(P, th);
+  const CovP c = load_cov(theta + 3 * th, P.cov);
+  double* reg = prior_reg(P, S, m, i);
+  const double* X = knots_of(P, m, i);
+  row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds);
+  Acc acc;
+  acc_cov(acc, X, P.r, X, P.r, c, true, 0.0);
+  for (int k = 0; k < m; ++k) gemm<Op::N, Op::T>(acc, reg + k * TT, T, reg + k * TT, T, T, -1.0, lds);
+  acc_to_lds(acc, lds);
+  __syncthreads();
+  if (!potrf_lds(lds) && threadIdx.x == 0) record_failure(P, S, m, i);
+  lds_to_global(lds, reg + m * TT);
+  trtri_lds_to_global(lds, reg + (m + 1) * TT);
+}
+
+// rows of W^ for the observations of one 64-row leaf tile
+__global__ __launch_bounds__(NT) void k_leaf_rows(DevPlan P, const double* theta, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int32_t* task = P.row_tasks + 2 * (t0 + blockIdx.x);
+  const int leaf = task[0];
+  const int64_t p0 = task[1];
+  double* S = slice(P, th);
+  const CovP c = load_cov(theta + 3 * th, P.cov);
+  const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
+  row_sweep(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wobs + p0 * T, P.plane, P.M, leaf, lds);
+}
+
+// Sigma_R = C_0(S_R, S_R) + tau^2 I - W^_R W^_R' per tile (bi >= bj)
+__global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int32_t* task = P.sig_tasks + 3 * (t0 + blockIdx.x);
+  const int leaf = task[0], bi = task[1], bj = task[2];
+  double* S = slice(P, th);
+  const CovP c = load_cov(theta + 3 * th, P.cov);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const int nR = P.leaf_n[leaf];
+  const int64_t pi = poff + (int64_t)T * bi, pj = poff + (int64_t)T * bj;
+  const int nvi = min(T, nR - T * bi), nvj = min(T, nR - T * bj);
+  Acc acc;
+  acc_cov(acc, P.obs_xy + 2 * pi, nvi, P.obs_xy + 2 * pj, nvj, c, bi == bj, c.tau2);
+  const double* W = S + P.off_wobs;
+  for (int k = 0; k < P.M; ++k)
+    gemm<Op::N, Op::T>(acc, W + k * P.plane + pi * T, T, W + k * P.plane + pj * T, T, T, -1.0, lds);
+  acc_store(acc, S + P.off_sig + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT, T);
+}
+
+// blocked right-looking Cholesky of one leaf's Sigma (tiles in place), the
+// inverses of its diagonal tiles, and d_R = log|Sigma_R|
+__global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int leaf = P.fac_tasks[t0 + blockIdx.x];
+  double* S = slice(P, th);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const int nR = P.leaf_n[leaf];
+  double* base = S + P.off_sig + P.leaf_soff[leaf] * TT;
+  double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
+  double logdet = 0.0;
+  bool ok = true;
+  Acc acc;
+  for (int kb = 0; kb < nb; ++kb) {
+    double* Dk = base + ((int64_t)kb * nb + kb) * TT;
+    tile_to_lds(Dk, T, lds);
+    __syncthreads();
+    ok = potrf_lds(lds) && ok;
+    logdet += 2.0 * logdiag_lds(lds, min(T, nR - kb * T), red);
+    lds_to_global(lds, Dk);
+    trtri_lds_to_global(lds, dinv + (int64_t)kb * TT);
+    for (int ib = kb + 1; ib < nb; ++ib) {
+      double* X = base + ((int64_t)ib * nb + kb) * TT;
+      acc_zero(acc);
+      gemm<Op::N, Op::T>(acc, X, T, dinv + (int64_t)kb * TT, T, T, 1.0, lds);
+      acc_store(acc, X, T);
+    }
+    __syncthreads();
+    for (int jb = kb + 1; jb < nb; ++jb)
+      for (int ib = jb; ib < nb; ++ib) {
+        double* X = base + ((int64_t)ib * nb + jb) * TT;
+        acc_load(acc, X, T);
+        gemm<Op::N, Op::T>(acc, base + ((int64_t)ib * nb + kb) * TT, T, base + ((int64_t)jb * nb + kb) * TT, T, T,
+                           -1.0, lds);
+        acc_store(acc, X, T);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    S[P.off_leafd + leaf] = logdet;
+    if (!ok) record_failure(P, S, P.M, leaf);
+  }
+}
+
+// Y = L_Sigma^{-1} X for one column plane of one leaf (forward substitution
+// by tiles with the inverted diagonal tiles)
+__global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int32_t* task = P.trsm_tasks + 2 * (t0 + blockIdx.x);
+  const int leaf = task[0], cpl = task[1];
+  double* S = slice(P, th);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const double* base = S + P.off_sig + P.leaf_soff[leaf] * TT;
+  const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
+  const double* X = S + P.off_wobs + cpl * P.plane + poff * T;
+  double* Y = S + P.off_y + cpl * P.plane + poff * T;
+  Acc acc;
+  for (int ib = 0; ib < nb; ++ib) {
+    acc_load(acc, X + (int64_t)ib * TT, T);
+    for (int jb = 0; jb < ib; ++jb)
+      gemm<Op::N, Op::N>(acc, base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, T, -1.0, lds);
+    acc_store(acc, Y + (int64_t)ib * TT, T);
+    __syncthreads();
+    acc_zero(acc);
+    gemm<Op::N, Op::N>(acc, dinv + (int64_t)ib * TT, T, Y + (int64_t)ib * TT, T, T, 1.0, lds);
+    acc_store(acc, Y + (int64_t)ib * TT, T);
+    __syncthreads();
+  }
+}
+
+// leaf products summed over the J leaves of a level-(M-1) region
+// (eq. helpquantities at m = M, eq. mainquantities):
+//   A^{k,l} = sum_c Y^k_c' Y^l_c, w^k = sum_c Y^k_c' y_c, u = sum_c y_c'y_c, d = sum_c d_c
+__global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int M = P.M;
+  const int nkl = M * (M + 1) / 2;
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t pidx = gid / nkl;
+  const int kl = (int)(gid % nkl);
+  int k, l;
+  kl_split(kl, k, l);
+  double* S = slice(P, th);
+  Post po = post_of(P, S, M - 1, pidx);
+  const double* Yk = S + P.off_y + k * P.plane;
+  const double* Yl = S + P.off_y + l * P.plane;
+  const double* Yz = S + P.off_y + (int64_t)M * P.plane;
+  Acc acc;
+  acc_zero(acc);
+  for (int c = 0; c < P.J; ++c) {
+    const int64_t leaf = pidx * P.J + c;
+    const int64_t p0 = P.leaf_poff[leaf], p1 = P.leaf_poff[leaf + 1];
+    for (int64_t p = p0; p < p1; p += T) gemm<Op::T, Op::N>(acc, Yk + p * T, T, Yl + p * T, T, T, 1.0, lds);
+  }
+  acc_store(acc, po.A(k, l), T);
+  if (k == l && threadIdx.x < T) {
+    double w = 0.0;
+    for (int c = 0; c < P.J; ++c) {
+      const int64_t leaf = pidx * P.J + c;
+      for (int64_t p = P.leaf_poff[leaf]; p < P.leaf_poff[leaf + 1]; ++p) w += Yk[p * T + threadIdx.x] * Yz[p * T];
+    }
+    po.omega(k)[threadIdx.x] = w;
+  }
+  if (kl == 0) {
+    double u = 0.0;
+    for (int c = 0; c < P.J; ++c) {
+      const int64_t leaf = pidx * P.J + c;
+      for (int64_t p = P.leaf_poff[leaf] + threadIdx.x; p < P.leaf_poff[leaf + 1]; p += NT) u += Yz[p * T] * Yz[p * T];
+    }
+    u = block_sum(u, red);
+    if (threadIdx.x == 0) {
+      double dsum = 0.0;
+      for (int c = 0; c < P.J; ++c) dsum += S[P.off_leafd + pidx * P.J + c];
+      *po.d() = dsum;
+      *po.u() = u;
+    }
+  }
+}
+
+// posterior level m: K~^{-1} = I + A^{m,m} (whitened), its factor and
+// inverse, Z = Lt^{-1} [A^{m,0..m-1} | w^m], d and u (Sec. 3.3)
+__global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_loglik, int64_t i0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int64_t i = i0 + blockIdx.x;
+  double* S = slice(P, th);
+  Post po = post_of(P, S, m, i);
+  tile_to_lds(po.A(m, m), T, lds);
+  __syncthreads();
+  if (threadIdx.x < T) lds[threadIdx.x * PLD + threadIdx.x] += 1.0;
+  __syncthreads();
+  const bool ok = potrf_lds(lds);
+  const double ld = 2.0 * logdiag_lds(lds, T, red);
+  lds_to_global(lds, po.Lt());
+  trtri_lds_to_global(lds, po.Lti());
+  Acc acc;
+  for (int l = 0; l < m; ++l) {
+    acc_zero(acc);
+    gemm<Op::N, Op::N>(acc, po.Lti(), T, po.A(m, l), T, T, 1.0, lds);
+    acc_store(acc, po.Z(l), T);
+  }
+  double zq = 0.0;
+  if (threadIdx.x < T) {
+    const double* Li = po.Lti() + threadIdx.x * T;
+    const double* w = po.omega(m);
+    for (int q = 0; q <= (int)threadIdx.x; ++q) zq += Li[q] * w[q];
+    po.zw()[threadIdx.x] = zq;
+  }
+  const double nrm = block_sum(zq * zq, red);
+  if (threadIdx.x == 0) {
+    const double dR = *po.d() + ld;
+    const double uR = *po.u() - nrm;
+    *po.d() = dR;
+    *po.u() = uR;
+    if (!ok) record_failure(P, S, m, i);
+    if (m == 0) {
+      const double ll = -0.5 * (dR + uR) - 0.5 * (double)P.n * 1.8378770664093453;
+      S[P.off_scal] = ll;
+      if (out_loglik) out_loglik[th] = ll;
+    }
+  }
+}
+
+// child sums for level m-1 (eq. mainquantities with eq. helpquantities):
+//   A^{k,l}_P = sum_c (A^{k,l}_c - Z^k_c' Z^l_c),  w^k_P = sum_c (w^k_c - Z^k_c' z_c)
+__global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int nkl = m * (m + 1) / 2;       // blocks k >= l <= m-1
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t pidx = gid / nkl;
+  const int kl = (int)(gid % nkl);
+  int k, l;
+  kl_split(kl, k, l);
+  double* S = slice(P, th);
+  Post pp = post_of(P, S, m - 1, pidx);
+  Acc acc;
+  acc_zero(acc);
+  for (int c = 0; c < P.J; ++c) {
+    Post pc = post_of(P, S, m, pidx * P.J + c);
+    acc_load(acc, pc.A(k, l), T, true);
+    gemm<Op::T, Op::N>(acc, pc.Z(k), T, pc.Z(l), T, T, -1.0, lds);
+  }
+  acc_store(acc, pp.A(k, l), T);
+  if (k == l && threadIdx.x < T) {
+    double w = 0.0;
+    for (int c = 0; c < P.J; ++c) {
+      Post pc = post_of(P, S, m, pidx * P.J + c);
+      double s = pc.omega(k)[threadIdx.x];
+      const double* Zk = pc.Z(k);
+      const double* zw = pc.zw();
+      for (int q = 0; q < T; ++q) s -= Zk[q * T + threadIdx.x] * zw[q];
+      w += s;
+    }
+    pp.omega(k)[threadIdx.x] = w;
+  }
+  if (kl == 0 && threadIdx.x == 0) {
+    double dsum = 0.0, usum = 0.0;
+    for (int c = 0; c < P.J; ++c) {
+      Post pc = post_of(P, S, m, pidx * P.J + c);
+      dsum += *pc.d();
+      usum += *pc.u();
+    }
+    *pp.d() = dsum;
+    *pp.u() = usum;
+  }
+}
+
+// M = 0: the single leaf is the root (exact Gaussian likelihood)
+__global__ __launch_bounds__(NT) void k_root_leaf(DevPlan P, double* out_loglik) {
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  double* S = slice(P, th);
+  const double* Yz = S + P.off_y;   // plane 0 = plane M
+  double u = 0.0;
+  for (int64_t p = threadIdx.x; p < P.npad; p += NT) u += Yz[p * T] * Yz[p * T];
+  u = block_sum(u, red);
+  if (threadIdx.x == 0) {
+    const double dR = S[P.off_leafd];
+    const double ll = -0.5 * (dR + u) - 0.5 * (double)P.n * 1.8378770664093453;
+    S[P.off_scal] = ll;
+    if (out_loglik) out_loglik[th] = ll;
+  }
+}
+
+// NaN for parameter vectors whose factorisations broke down
+__global__ void k_mark_failed(DevPlan P, double* out, int width) {
+  const int th = blockIdx.x;
+  const double* S = slice(P, th);
+  if (*(const unsigned long long*)(S + P.off_status) != 0ull && threadIdx.x < width)
+    out[th * width + threadIdx.x] = __builtin_nan("");
+}
+
+// ------------------------------------------------------------------ launches
+hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
+                          hipStream_t st) {
+  const DevPlan& P = H.dp;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0};
+  int64_t gx = (P.plane + NT - 1) / NT;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
+  for (int m = 0; m < M; ++m) run(k_prior, P.nreg[m], theta, m);
+  run(k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
+  run(k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
+  run(k_leaf_potrf, (int64_t)H.fac_tasks.size());
+  run(k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
+  if (M == 0) {
+    hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
+  } else {
+    run(k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    for (int m = M - 1; m >= 0; --m) {
+      run(k_post, P.nreg[m], m, out_loglik);
+      if (m > 0) run(k_post_reduce, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+    }
+  }
+  if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);
+  return hipGetLastError();
+}
+
+}  // namespace mra

@@ -1,0 +1,350 @@
+// Host plan builder: recursive partition and knots (Sec. 2.2, 2.5), leaf
+// assignment, padded leaf-sorted storage, arena layout and task lists.
+//
+// Partition rules (fixed so that independent implementations agree bit for
+// bit): d = 2, J = 4 splits each box at 0.5*(a+b) per axis, child
+// 2*[y >= ymid] + [x >= xmid]; d = 1 splits at a + ((b-a)*j)/J and the child
+// is the number of split points <= x; J = 1 keeps the box.  Default knots:
+// cell-centred g x g grid (d = 2, g = sqrt(r)), x_i = a + ((b-a)*(2i+1))/(2g),
+// index iy*g + ix; d = 1: x_i = a + ((b-a)*(2i+1))/(2r).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "plan.hpp"
+
+namespace mra {
+namespace {
+
+struct Box {
+  double a[2], b[2];
+};
+
+Box child_box(const Box& p, int j, int d, int J) {
+  Box c = p;
+  if (J == 1) return c;
+  if (d == 2) {
+    int bx = j & 1, by = j >> 1;
+    double xm = 0.5 * (p.a[0] + p.b[0]);
+    double ym = 0.5 * (p.a[1] + p.b[1]);
+    if (bx) c.a[0] = xm; else c.b[0] = xm;
+    if (by) c.a[1] = ym; else c.b[1] = ym;
+    return c;
+  }
+  double a = p.a[0], b = p.b[0];
+  c.a[0] = (j == 0) ? a : a + ((b - a) * (double)j) / (double)J;
+  c.b[0] = (j == J - 1) ? b : a + ((b - a) * (double)(j + 1)) / (double)J;
+  return c;
+}
+
+int child_of(const Box& p, const double* x, int d, int J) {
+  if (J == 1) return 0;
+  if (d == 2) {
+    double xm = 0.5 * (p.a[0] + p.b[0]);
+    double ym = 0.5 * (p.a[1] + p.b[1]);
+    return 2 * (x[1] >= ym ? 1 : 0) + (x[0] >= xm ? 1 : 0);
+  }
+  double a = p.a[0], b = p.b[0];
+  int c = 0;
+  for (int k = 1; k < J; ++k)
+    if (x[0] >= a + ((b - a) * (double)k) / (double)J) ++c;
+  return c;
+}
+
+// leaf index of every point; returns false if a point is outside or not finite
+bool assign_leaves(const std::vector<std::vector<Box>>& boxes, const double* pts, int64_t n, int d, int J, int M,
+                   const double* lo, const double* hi, std::vector<int64_t>& leaf) {
+  leaf.assign(n, 0);
+  for (int64_t p = 0; p < n; ++p) {
+    const double* x = pts + p * d;
+    for (int a = 0; a < d; ++a)
+      if (!std::isfinite(x[a]) || x[a] < lo[a] || x[a] > hi[a]) return false;
+    int64_t i = 0;
+    for (int m = 0; m < M; ++m) i = i * J + child_of(boxes[m][i], x, d, J);
+    leaf[p] = i;
+  }
+  return true;
+}
+
+// stable sort by leaf: perm[k] = original index, off = CSR offsets
+void sort_by_leaf(const std::vector<int64_t>& leaf, int64_t n_leaves, std::vector<int64_t>& perm,
+                  std::vector<int64_t>& off) {
+  off.assign(n_leaves + 1, 0);
+  for (int64_t v : leaf) off[v + 1]++;
+  for (int64_t i = 0; i < n_leaves; ++i) off[i + 1] += off[i];
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  perm.assign(leaf.size(), 0);
+  for (int64_t p = 0; p < (int64_t)leaf.size(); ++p) perm[pos[leaf[p]]++] = p;
+}
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, const double* h_pred, int64_t n_pred,
+                      const double* h_knots, mra_plan_s* P) {
+  if (!cfg || (!h_locs && n > 0) || n < 1 || n_pred < 0 || (n_pred > 0 && !h_pred)) return MRA_EINVAL;
+  const int d = cfg->d, M = cfg->M, J = cfg->J, r = cfg->r;
+  if (d < 1 || d > 2 || M < 0 || M >= MAXL || r < 1 || r > T || cfg->max_theta < 1) return MRA_EINVAL;
+  if (d == 2 && J != 1 && J != 4) return MRA_EINVAL;
+  if (d == 1 && (J < 1 || J > 8)) return MRA_EINVAL;
+  if (cfg->cov != MRA_COV_EXPONENTIAL && cfg->cov != MRA_COV_MATERN32) return MRA_EINVAL;
+  for (int a = 0; a < d; ++a)
+    if (!(cfg->lo[a] < cfg->hi[a]) || !std::isfinite(cfg->lo[a]) || !std::isfinite(cfg->hi[a])) return MRA_EINVAL;
+  int g = 0;
+  if (!h_knots && d == 2) {
+    g = (int)std::lround(std::sqrt((double)r));
+    if (g * g != r) return MRA_EINVAL;
+  }
+  P->cfg = *cfg;
+  P->d = d; P->M = M; P->J = J; P->r = r; P->n = n; P->n_pred = n_pred;
+  // levels
+  P->nreg.assign(M + 1, 1);
+  for (int m = 1; m <= M; ++m) P->nreg[m] = P->nreg[m - 1] * J;
+  P->reg_base.assign(M + 1, 0);
+  for (int m = 1; m <= M; ++m) P->reg_base[m] = P->reg_base[m - 1] + P->nreg[m - 1];
+  const int64_t n_internal = P->reg_base[M];
+  const int64_t n_leaves = P->nreg[M];
+  // boxes
+  std::vector<std::vector<Box>> boxes(M + 1);
+  Box root;
+  for (int a = 0; a < 2; ++a) { root.a[a] = a < d ? cfg->lo[a] : 0.0; root.b[a] = a < d ? cfg->hi[a] : 0.0; }
+  boxes[0].push_back(root);
+  for (int m = 0; m < M; ++m) {
+    boxes[m + 1].resize(P->nreg[m + 1]);
+    for (int64_t i = 0; i < P->nreg[m]; ++i)
+      for (int j = 0; j < J; ++j) boxes[m + 1][i * J + j] = child_box(boxes[m][i], j, d, J);
+  }
+  // knots
+  P->knots.assign((size_t)n_internal * r * d, 0.0);
+  if (h_knots) {
+    for (size_t q = 0; q < P->knots.size(); ++q) {
+      if (!std::isfinite(h_knots[q])) return MRA_EINVAL;
+      P->knots[q] = h_knots[q];
+    }
+  } else {
+    for (int m = 0; m < M; ++m)
+      for (int64_t i = 0; i < P->nreg[m]; ++i) {
+        const Box& b = boxes[m][i];
+        double* kn = P->knots.data() + (size_t)(P->reg_base[m] + i) * r * d;
+        if (d == 2) {
+          for (int iy = 0; iy < g; ++iy)
+            for (int ix = 0; ix < g; ++ix) {
+              kn[(iy * g + ix) * 2 + 0] = b.a[0] + ((b.b[0] - b.a[0]) * (double)(2 * ix + 1)) / (double)(2 * g);
+              kn[(iy * g + ix) * 2 + 1] = b.a[1] + ((b.b[1] - b.a[1]) * (double)(2 * iy + 1)) / (double)(2 * g);
+            }
+        } else {
+          for (int k = 0; k < r; ++k)
+            kn[k] = b.a[0] + ((b.b[0] - b.a[0]) * (double)(2 * k + 1)) / (double)(2 * r);
+        }
+      }
+  }
+  P->knot_xy.assign((size_t)std::max<int64_t>(n_internal, 1) * T * 2, 0.0);
+  for (int64_t q = 0; q < n_internal; ++q)
+    for (int k = 0; k < r; ++k)
+      for (int a = 0; a < d; ++a) P->knot_xy[(q * T + k) * 2 + a] = P->knots[(q * r + k) * d + a];
+  // observations
+  std::vector<int64_t> leaf;
+  if (!assign_leaves(boxes, h_locs, n, d, J, M, cfg->lo, cfg->hi, leaf)) return MRA_EINVAL;
+  sort_by_leaf(leaf, n_leaves, P->perm, P->leaf_off);
+  P->leaf_n.assign(n_leaves, 0);
+  P->leaf_poff.assign(n_leaves + 1, 0);
+  P->leaf_soff.assign(n_leaves, 0);
+  P->leaf_doff.assign(n_leaves, 0);
+  int64_t soff = 0, doff = 0;
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    int64_t c = P->leaf_off[i + 1] - P->leaf_off[i];
+    P->leaf_n[i] = (int32_t)c;
+    P->max_leaf = std::max(P->max_leaf, c);
+    int64_t nb = (c + T - 1) / T;
+    P->leaf_poff[i + 1] = P->leaf_poff[i] + nb * T;
+    P->leaf_soff[i] = soff;
+    P->leaf_doff[i] = doff;
+    soff += nb * nb;
+    doff += nb;
+  }
+  P->npad = std::max<int64_t>(P->leaf_poff[n_leaves], T);
+  P->n_sig_tiles = std::max<int64_t>(soff, 1);
+  P->n_dinv_tiles = std::max<int64_t>(doff, 1);
+  P->obs_xy.assign(P->npad * 2, 0.0);
+  P->obs_gidx.assign(P->npad, -1);
+  for (int64_t i = 0; i < n_leaves; ++i)
+    for (int64_t k = 0; k < P->leaf_n[i]; ++k) {
+      int64_t src = P->perm[P->leaf_off[i] + k];
+      int64_t dst = P->leaf_poff[i] + k;
+      for (int a = 0; a < d; ++a) P->obs_xy[dst * 2 + a] = h_locs[src * d + a];
+      P->obs_gidx[dst] = src;
+    }
+  // prediction locations
+  std::vector<int64_t> pleaf;
+  if (n_pred > 0 && !assign_leaves(boxes, h_pred, n_pred, d, J, M, cfg->lo, cfg->hi, pleaf)) return MRA_EINVAL;
+  sort_by_leaf(pleaf, n_leaves, P->pperm, P->pleaf_off);
+  P->pleaf_n.assign(n_leaves, 0);
+  P->pleaf_poff.assign(n_leaves + 1, 0);
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    int64_t c = P->pleaf_off[i + 1] - P->pleaf_off[i];
+    P->pleaf_n[i] = (int32_t)c;
+    P->pleaf_poff[i + 1] = P->pleaf_poff[i] + (c + T - 1) / T * T;
+  }
+  P->ppad = std::max<int64_t>(P->pleaf_poff[n_leaves], T);
+  P->pred_xy.assign(P->ppad * 2, 0.0);
+  P->pred_gidx.assign(P->ppad, -1);
+  for (int64_t i = 0; i < n_leaves; ++i)
+    for (int64_t k = 0; k < P->pleaf_n[i]; ++k) {
+      int64_t src = P->pperm[P->pleaf_off[i] + k];
+      int64_t dst = P->pleaf_poff[i] + k;
+      for (int a = 0; a < d; ++a) P->pred_xy[dst * 2 + a] = h_pred[src * d + a];
+      P->pred_gidx[dst] = src;
+    }
+  // task lists; leaves are visited largest first so that long factorisations start early
+  std::vector<int32_t> order(n_leaves);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return P->leaf_n[x] > P->leaf_n[y]; });
+  P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->pred_tasks.clear();
+  for (int32_t i : order) {
+    int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
+    if (nb == 0) continue;
+    P->fac_tasks.push_back(i);
+    for (int64_t t = 0; t < nb; ++t) { P->row_tasks.push_back(i); P->row_tasks.push_back((int32_t)(P->leaf_poff[i] + t * T)); }
+    for (int64_t bi = 0; bi < nb; ++bi)
+      for (int64_t bj = 0; bj <= bi; ++bj) {
+        P->sig_tasks.push_back(i); P->sig_tasks.push_back((int32_t)bi); P->sig_tasks.push_back((int32_t)bj);
+      }
+    for (int c = 0; c <= M; ++c) { P->trsm_tasks.push_back(i); P->trsm_tasks.push_back(c); }
+  }
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    int64_t nb = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;
+    for (int64_t t = 0; t < nb; ++t) {
+      P->pred_tasks.push_back((int32_t)i); P->pred_tasks.push_back((int32_t)(P->pleaf_poff[i] + t * T));
+    }
+  }
+  if (P->npad > INT32_MAX || P->ppad > INT32_MAX) return MRA_EINVAL;
+
+  // ---- geometry arena layout (bytes, 256-aligned) ----
+  Layout& L = P->lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
+  L.g_knot = take(P->knot_xy.size() * 8);
+  L.g_obs = take(P->obs_xy.size() * 8);
+  L.g_gidx = take(P->obs_gidx.size() * 8);
+  L.g_leafn = take(P->leaf_n.size() * 4);
+  L.g_poff = take(P->leaf_poff.size() * 8);
+  L.g_soff = take(P->leaf_soff.size() * 8);
+  L.g_doff = take(P->leaf_doff.size() * 8);
+  L.g_rowt = take(std::max<size_t>(P->row_tasks.size(), 1) * 4);
+  L.g_sigt = take(std::max<size_t>(P->sig_tasks.size(), 1) * 4);
+  L.g_fact = take(std::max<size_t>(P->fac_tasks.size(), 1) * 4);
+  L.g_trst = take(std::max<size_t>(P->trsm_tasks.size(), 1) * 4);
+  L.g_pxy = take(P->pred_xy.size() * 8);
+  L.g_pgidx = take(P->pred_gidx.size() * 8);
+  L.g_pt = take(std::max<size_t>(P->pred_tasks.size(), 1) * 4);
+  L.g_pleafn = take(P->pleaf_n.size() * 4);
+  L.geom_bytes = off;
+
+  // ---- work arena layout (doubles per theta slice) ----
+  DevPlan& D = P->dp;
+  D = DevPlan{};
+  D.d = d; D.M = M; D.J = J; D.r = r; D.cov = cfg->cov;
+  D.n = n; D.npad = P->npad; D.n_leaves = n_leaves; D.ppad = P->ppad; D.n_pred = n_pred;
+  int64_t w = 0;
+  auto wtake = [&](int64_t doubles) { int64_t o = w; w = round_up(w + doubles, 32); return o; };
+  for (int m = 0; m <= M; ++m) { D.nreg[m] = P->nreg[m]; D.reg_base[m] = P->reg_base[m]; }
+  for (int m = 0; m < M; ++m) D.prior_off[m] = wtake(P->nreg[m] * (m + 2) * TT);
+  D.plane = P->npad * T;
+  D.off_wobs = wtake((M + 1) * D.plane);
+  D.off_sig = wtake(P->n_sig_tiles * TT);
+  D.off_dinv = wtake(P->n_dinv_tiles * TT);
+  D.off_y = wtake((M + 1) * D.plane);
+  D.off_leafd = wtake(n_leaves);
+  D.off_status = wtake(4);
+  D.off_scal = wtake(16);
+  for (int m = 0; m < M; ++m) {
+    int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
+    // A tiles, omega, Ltilde, Ltilde^{-1}, Z tiles, z_omega, d, u
+    D.post_stride[m] = round_up(nA * TT + (m + 1) * T + 2 * TT + m * TT + T + 2, 32);
+    D.post_off[m] = wtake(P->nreg[m] * D.post_stride[m]);
+  }
+  // reverse pass: per internal region G row tiles (m+1), omega-bar (T),
+  // T-sums ((m+1)(m+2)/2 tiles), W-bar rows (m tiles) and W-bar^m (1 tile)
+  for (int m = 0; m < M; ++m) {
+    int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
+    D.grad_stride[m] = round_up((m + 1) * TT + T + nA * TT + m * TT + TT, 32);
+    D.grad_off[m] = wtake(P->nreg[m] * D.grad_stride[m]);
+  }
+  D.off_v = wtake((M + 1) * D.plane);
+  D.off_q = wtake((M + 1) * D.plane);
+  D.off_sbar = wtake(P->n_sig_tiles * TT);
+  D.off_wbar = wtake(std::max(M, 1) * D.plane);
+  // gradient partial sums: one slot per task of every gradient-producing launch
+  D.n_gpart = (int64_t)P->sig_tasks.size() / 3 + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
+  D.off_gpart = wtake(D.n_gpart * 4);
+  D.off_pw = wtake(std::max(M, 1) * P->ppad * T);
+  D.off_pl = 0;
+  D.theta_stride = w;
+  L.theta_stride = w;
+
+  // ---- algorithmic flop model (actual r, not the padded tile) ----
+  const double rr = r;
+  double fl = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double per = 0.0;
+    for (int l = 0; l < m; ++l) per += 2.0 * rr * rr * (l * rr) + rr * rr * rr;   // GEMM + TRSM
+    per += rr * rr * (m * rr) + rr * rr * rr / 3.0;                                  // SYRK + POTRF
+    fl += per * P->nreg[m];
+  }
+  double fl_post = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double per = rr * rr * rr / 3.0 + rr * rr * (m * rr + 1) + (m * rr + 1) * (m * rr + 1) * rr;
+    fl_post += per * P->nreg[m];
+  }
+  double fl_leaf = 0.0;
+  const double Mr = M * rr;
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    double nr = P->leaf_n[i];
+    if (nr == 0) continue;
+    fl_leaf += nr * rr * rr * (double)(M * (M - 1) + M);     // rows of W^ (GEMM + TRSM)
+    fl_leaf += nr * nr * Mr;                                 // Sigma (SYRK)
+    fl_leaf += nr * nr * nr / 3.0;                           // POTRF
+    fl_leaf += nr * nr * (Mr + 1);                           // TRSM of [W^ | z]
+    fl_leaf += nr * (Mr + 1) * (Mr + 1);                     // [W^ | z]' Sigma^{-1} [W^ | z] (SYRK)
+  }
+  P->flops_loglik = fl + fl_post + fl_leaf;
+  // reverse pass: the posterior reverse needs V, V Fbar and V Fbar V' per
+  // region; the leaf reverse V, Q = V Fbar, Sigma-bar, W^-bar; the prior
+  // reverse mirrors the row sweeps plus the T reductions
+  double rv = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double k = m * rr + 1;
+    rv += P->nreg[m] * (rr * rr * k + 2.0 * rr * k * k + 2.0 * rr * rr * k + 2.0 * rr * rr * rr);
+    double per = 0.0;
+    for (int l = 0; l < m; ++l) per += 2.0 * rr * rr * (l * rr) + 2.0 * rr * rr * rr + 2.0 * rr * rr * ((l + 1) * rr);
+    rv += per * P->nreg[m] + 4.0 * rr * rr * rr * P->nreg[m];
+  }
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    double nr = P->leaf_n[i];
+    if (nr == 0) continue;
+    rv += nr * nr * (Mr + 1);                 // V = L^{-T} Y
+    rv += 2.0 * nr * (Mr + 1) * (Mr + 1);     // Q = V Fbar
+    rv += 2.0 * nr * nr * (Mr + 1);           // Sigma-bar = -Q V'
+    rv += 2.0 * nr * nr * nr / 3.0;           // Sigma^{-1}
+    rv += 2.0 * nr * nr * Mr;                 // Sigma-bar W^
+    double per = 0.0;                         // per row: W-bar^l, W^-bar updates, T contributions
+    for (int l = 0; l < M; ++l) per += 2.0 * rr * rr + 2.0 * rr * rr * l + 2.0 * rr * rr * (l + 1);
+    rv += nr * per;
+  }
+  P->flops_grad = P->flops_loglik + rv;
+  double fp = 0.0;
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    double np = P->pleaf_n[i], nr = P->leaf_n[i];
+    if (np == 0) continue;
+    fp += np * rr * rr * (double)(M * (M - 1) + M);     // U^ rows
+    fp += 2.0 * np * nr * Mr + np * nr * nr;             // L^M and L^M L^{-T}
+    fp += 2.0 * np * nr * Mr;                            // B~^M
+    for (int l = 0; l < M; ++l) fp += np * (rr * rr + 2.0 * rr * rr * l);
+  }
+  P->flops_predict = fp;
+  return MRA_OK;
+}
+
+}  // namespace mra

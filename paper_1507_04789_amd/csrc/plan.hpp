@@ -1,0 +1,65 @@
+// Host-side M-RA plan: partition, knots, leaf-sorted padded observations,
+// work-arena layout and task lists.  Built without touching the GPU.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mra.h"
+#include "devplan.hpp"
+
+namespace mra {
+
+struct GraphCache;  // defined in api.cpp
+
+struct Layout {
+  // geometry arena (byte offsets)
+  size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst;
+  size_t g_pxy, g_pgidx, g_pt, g_pleafn, geom_bytes;
+  // work arena (doubles per theta slice)
+  int64_t theta_stride;
+};
+
+}  // namespace mra
+
+struct mra_plan_s {
+  mra_config cfg;
+  int d, M, J, r;
+  int64_t n, n_pred;
+  std::vector<double> knots;          // (sum_{m<M} J^m) x r x d, as built
+  std::vector<int64_t> nreg, reg_base;
+  std::vector<int64_t> perm;          // leaf order -> original index
+  std::vector<int64_t> leaf_off;      // CSR offsets (unpadded)
+  std::vector<int32_t> leaf_n;
+  std::vector<int64_t> leaf_poff, leaf_soff, leaf_doff;
+  int64_t npad = 0, n_sig_tiles = 0, n_dinv_tiles = 0, max_leaf = 0;
+  std::vector<double> obs_xy;         // npad x 2
+  std::vector<int64_t> obs_gidx;      // npad
+  std::vector<double> knot_xy;        // n_internal x T x 2
+  // prediction
+  std::vector<int64_t> pperm, pleaf_off;
+  std::vector<int32_t> pleaf_n;
+  std::vector<int64_t> pleaf_poff;
+  int64_t ppad = 0;
+  std::vector<double> pred_xy;
+  std::vector<int64_t> pred_gidx;
+  // task lists
+  std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, pred_tasks;
+  // layout
+  mra::Layout lay;
+  mra::DevPlan dp;
+  bool bound = false;
+  void* d_geom = nullptr;
+  void* d_work = nullptr;
+  double flops_loglik = 0, flops_grad = 0, flops_predict = 0;
+  // failure of the last synchronised call
+  int32_t fail_theta = -1, fail_level = -1;
+  int64_t fail_region = -1;
+  mra::GraphCache* graphs = nullptr;
+};
+
+namespace mra {
+mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, const double* h_pred,
+                      int64_t n_pred, const double* h_knots, mra_plan_s* P);
+}  // namespace mra
