@@ -186,12 +186,13 @@ def _make_autograd():
         def forward(ctx, theta, plan, y):
             ll, g = plan.loglik_grad(y, theta.detach())
             ctx.save_for_backward(g)
+            ctx.theta_device = theta.device
             return ll
 
         @staticmethod
         def backward(ctx, gout):
             (g,) = ctx.saved_tensors
-            return gout[:, None] * g, None, None
+            return (gout.to(g.device)[:, None] * g).to(ctx.theta_device), None, None
 
     return MRALogLik
 

@@ -124,10 +124,12 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
             up(L.g_sigt, P->sig_tasks.data(), P->sig_tasks.size() * 4) &&
             up(L.g_fact, P->fac_tasks.data(), P->fac_tasks.size() * 4) &&
             up(L.g_trst, P->trsm_tasks.data(), P->trsm_tasks.size() * 4) &&
+            up(L.g_lint, P->linv_tasks.data(), P->linv_tasks.size() * 4) &&
             up(L.g_pxy, P->pred_xy.data(), P->pred_xy.size() * 8) &&
             up(L.g_pgidx, P->pred_gidx.data(), P->pred_gidx.size() * 8) &&
             up(L.g_pt, P->pred_tasks.data(), P->pred_tasks.size() * 4) &&
-            up(L.g_pleafn, P->pleaf_n.data(), P->pleaf_n.size() * 4);
+            up(L.g_pleafn, P->pleaf_n.data(), P->pleaf_n.size() * 4) &&
+            up(L.g_ppoff, P->pleaf_poff.data(), P->pleaf_poff.size() * 8);
   if (!ok || hipStreamSynchronize(st) != hipSuccess) return MRA_EHIP;
   DevPlan& D = P->dp;
   D.knot_xy = (const double*)(g + L.g_knot);
@@ -141,10 +143,12 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   D.sig_tasks = (const int32_t*)(g + L.g_sigt);
   D.fac_tasks = (const int32_t*)(g + L.g_fact);
   D.trsm_tasks = (const int32_t*)(g + L.g_trst);
+  D.linv_tasks = (const int32_t*)(g + L.g_lint);
   D.pred_xy = (const double*)(g + L.g_pxy);
   D.pred_gidx = (const int64_t*)(g + L.g_pgidx);
   D.pred_tasks = (const int32_t*)(g + L.g_pt);
   D.pleaf_n = (const int32_t*)(g + L.g_pleafn);
+  D.pleaf_poff = (const int64_t*)(g + L.g_ppoff);
   D.work = (double*)d_work;
   P->d_geom = d_geom;
   P->d_work = d_work;

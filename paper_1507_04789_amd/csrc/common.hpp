@@ -1,0 +1,95 @@
+// Device helpers shared by the forward, reverse and prediction kernels:
+// arena addressing of the per-region storage and the row sweep of eq. priorw.
+#pragma once
+#include "cov.hpp"
+
+namespace mra {
+
+__device__ __forceinline__ double* slice(const DevPlan& P, int th) { return P.work + (int64_t)th * P.theta_stride; }
+
+__device__ __forceinline__ double* prior_reg(const DevPlan& P, double* S, int m, int64_t i) {
+  return S + P.prior_off[m] + i * (int64_t)(m + 2) * TT;
+}
+__device__ __forceinline__ const double* knots_of(const DevPlan& P, int m, int64_t i) {
+  return P.knot_xy + (P.reg_base[m] + i) * (2 * T);
+}
+__device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, int l) {
+  for (int q = m; q > l; --q) i /= P.J;
+  return i;
+}
+__device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
+__device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
+  k = 0;
+  while ((k + 1) * (k + 2) / 2 <= kl) ++k;
+  l = kl - k * (k + 1) / 2;
+}
+
+// posterior storage of region (m, i)
+struct Post {
+  double* base;
+  int m;
+  __device__ double* A(int k, int l) const { return base + (int64_t)kl_index(k, l) * TT; }
+  __device__ double* omega(int k) const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + k * T; }
+  __device__ double* Lt() const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + (m + 1) * T; }
+  __device__ double* Lti() const { return Lt() + TT; }
+  __device__ double* Z(int l) const { return Lt() + 2 * TT + (int64_t)l * TT; }
+  __device__ double* zw() const { return Lt() + 2 * TT + (int64_t)m * TT; }
+  __device__ double* d() const { return zw() + T; }
+  __device__ double* u() const { return zw() + T + 1; }
+};
+__device__ __forceinline__ Post post_of(const DevPlan& P, double* S, int m, int64_t i) {
+  Post p;
+  p.base = S + P.post_off[m] + i * P.post_stride[m];
+  p.m = m;
+  return p;
+}
+
+__device__ __forceinline__ void record_failure(const DevPlan& P, double* S, int level, int64_t region) {
+  atomicCAS((unsigned long long*)(S + P.off_status), 0ull, (unsigned long long)fail_code(level, region));
+}
+
+// Row sweep of eq. priorw for 64 rows (points X, nx valid) of a region at
+// level `lev` with index `idx`: writes W^^l (l < lev) to rows + l*bstride.
+__device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
+                          int64_t bstride, int lev, int64_t idx, double* lds) {
+  Acc acc;
+  for (int l = 0; l < lev; ++l) {
+    const int64_t al = ancestor(P, lev, idx, l);
+    const double* Pa = prior_reg(P, S, l, al);
+    acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
+    for (int k = 0; k < l; ++k) gemm<Op::N, Op::T>(acc, rows + k * bstride, T, Pa + k * TT, T, T, -1.0, lds);
+    double* out = rows + l * bstride;
+    acc_store(acc, out, T);
+    __syncthreads();
+    acc_zero(acc);
+    gemm<Op::N, Op::T>(acc, out, T, Pa + (l + 1) * TT, T, T, 1.0, lds);   // W^l L_{a_l}^{-T}
+    acc_store(acc, out, T);
+    __syncthreads();
+  }
+}
+
+
+// reverse-pass storage of region (m, i):
+//   G(l), l <= m   cotangent of A^{m,l} of this region (row m of the posterior cotangent)
+//   wbar_omega()   cotangent of w^m
+//   Tsum(l, k)     sum over the subtree's rows of W-bar^l' W^^k, k <= l <= m
+//   Wbar(l), l < m cotangent rows of W^^l, then W-bar^l, of the region's knots
+//   scratch()      one tile
+struct Grad {
+  double* base;
+  int m;
+  __device__ int64_t nA() const { return (int64_t)(m + 1) * (m + 2) / 2; }
+  __device__ double* G(int l) const { return base + (int64_t)l * TT; }
+  __device__ double* wbar_omega() const { return base + (int64_t)(m + 1) * TT; }
+  __device__ double* Tsum(int l, int k) const { return base + (int64_t)(m + 1) * TT + T + (int64_t)kl_index(l, k) * TT; }
+  __device__ double* Wbar(int l) const { return base + (int64_t)(m + 1) * TT + T + nA() * TT + (int64_t)l * TT; }
+  __device__ double* scratch() const { return base + (int64_t)(m + 1) * TT + T + nA() * TT + (int64_t)m * TT; }
+};
+__device__ __forceinline__ Grad grad_of(const DevPlan& P, double* S, int m, int64_t i) {
+  Grad g;
+  g.base = S + P.grad_off[m] + i * P.grad_stride[m];
+  g.m = m;
+  return g;
+}
+
+}  // namespace mra

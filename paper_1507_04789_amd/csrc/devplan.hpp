@@ -31,10 +31,13 @@ struct DevPlan {
   const int32_t* sig_tasks;  // [n_sig_tasks][3] (leaf, bi, bj), bi >= bj
   const int32_t* fac_tasks;  // [n_fac_tasks] nonempty leaves, largest first
   const int32_t* trsm_tasks; // [n_trsm_tasks][2] (leaf, column plane 0..M)
+  const int32_t* linv_tasks; // [n_linv_tasks][2] (leaf, tile column j)
+  int64_t n_sig_tasks, n_row_tasks;
   const double* pred_xy;     // [ppad][2]
   const int64_t* pred_gidx;  // [ppad]
   const int32_t* pred_tasks; // [n_pred_tasks][2] (leaf, first padded prediction row)
   const int32_t* pleaf_n;    // [n_leaves]
+  const int64_t* pleaf_poff; // [n_leaves + 1]
 
   // level tables
   int64_t nreg[MAXL];        // J^m
@@ -60,12 +63,14 @@ struct DevPlan {
   int64_t off_v;       // (M+1) planes: V = L_Sigma^{-T} Y
   int64_t off_q;       // (M+1) planes: Q = V Fbar
   int64_t off_sbar;    // Sigma-bar tiles (same layout as off_sig)
+  int64_t off_linv;    // tiles of L_Sigma^{-1} (same layout as off_sig)
   int64_t off_wbar;    // M planes: cotangent of the leaf rows of W^ (then W-bar)
   int64_t off_gpart;   // gradient partial sums, [n_gpart][4]
   int64_t n_gpart;
   // prediction
   int64_t off_pw;      // M planes [ppad][T] of U^ rows, then B~ rows
-  int64_t off_pl;      // [ppad][T * nbmax] scratch for L^M rows
+  int64_t off_pl;      // per prediction tile pl_stride doubles: L^M, then E, tiles
+  int64_t pl_stride;
 };
 
 }  // namespace mra

@@ -11,75 +11,11 @@
 // W^^k_R, and the posterior precision of xi_R given the finer levels is
 // I + A^{m,m}_R (the whitened K~^{-1}).  log|K~^{-1}| - log|K^{-1}| =
 // log|I + A^{m,m}|, so the d and u recursions of Sec. 3.3 keep their form.
-#include "cov.hpp"
+#include "common.hpp"
 #include "plan.hpp"
 #include "launch.hpp"
 
 namespace mra {
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double* slice(const DevPlan& P, int th) { return P.work + (int64_t)th * P.theta_stride; }
-
-__device__ __forceinline__ double* prior_reg(const DevPlan& P, double* S, int m, int64_t i) {
-  return S + P.prior_off[m] + i * (int64_t)(m + 2) * TT;
-}
-__device__ __forceinline__ const double* knots_of(const DevPlan& P, int m, int64_t i) {
-  return P.knot_xy + (P.reg_base[m] + i) * (2 * T);
-}
-__device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, int l) {
-  for (int q = m; q > l; --q) i /= P.J;
-  return i;
-}
-__device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
-__device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
-  k = 0;
-  while ((k + 1) * (k + 2) / 2 <= kl) ++k;
-  l = kl - k * (k + 1) / 2;
-}
-
-// posterior storage of region (m, i)
-struct Post {
-  double* base;
-  int m;
-  __device__ double* A(int k, int l) const { return base + (int64_t)kl_index(k, l) * TT; }
-  __device__ double* omega(int k) const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + k * T; }
-  __device__ double* Lt() const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + (m + 1) * T; }
-  __device__ double* Lti() const { return Lt() + TT; }
-  __device__ double* Z(int l) const { return Lt() + 2 * TT + (int64_t)l * TT; }
-  __device__ double* zw() const { return Lt() + 2 * TT + (int64_t)m * TT; }
-  __device__ double* d() const { return zw() + T; }
-  __device__ double* u() const { return zw() + T + 1; }
-};
-__device__ __forceinline__ Post post_of(const DevPlan& P, double* S, int m, int64_t i) {
-  Post p;
-  p.base = S + P.post_off[m] + i * P.post_stride[m];
-  p.m = m;
-  return p;
-}
-
-__device__ __forceinline__ void record_failure(const DevPlan& P, double* S, int level, int64_t region) {
-  atomicCAS((unsigned long long*)(S + P.off_status), 0ull, (unsigned long long)fail_code(level, region));
-}
-
-// Row sweep of eq. priorw for 64 rows (points X, nx valid) of a region at
-// level `lev` with index `idx`: writes W^^l (l < lev) to rows + l*bstride.
-__device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
-                          int64_t bstride, int lev, int64_t idx, double* lds) {
-  Acc acc;
-  for (int l = 0; l < lev; ++l) {
-    const int64_t al = ancestor(P, lev, idx, l);
-    const double* Pa = prior_reg(P, S, l, al);
-    acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
-    for (int k = 0; k < l; ++k) gemm<Op::N, Op::T>(acc, rows + k * bstride, T, Pa + k * TT, T, T, -1.0, lds);
-    double* out = rows + l * bstride;
-    acc_store(acc, out, T);
-    __syncthreads();
-    acc_zero(acc);
-    gemm<Op::N, Op::T>(acc, out, T, Pa + (l + 1) * TT, T, T, 1.0, lds);   // W^l L_{a_l}^{-T}
-    acc_store(acc, out, T);
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------------ kernels
 

@@ -1,13 +1,523 @@
-// Reverse pass (gradient) of the M-RA log-likelihood.
-#include "cov.hpp"
+// Reverse pass of the M-RA log-likelihood: d loglik / d(log sigma^2,
+// log kappa, log tau^2), hand-written adjoint of the forward kernels.
+//
+// Every posterior step (a region's, and the leaves' definitions) has the
+// form F = X' P^{-1} X, d += log|P|, with X = [A^{m,<m} | w^m] and
+// P = I + A^{m,m} (whitened K~^{-1}) at a region, X = [W^_R | z_R] and
+// P = Sigma_R at a leaf; the outputs are A~ = A - F_AA, w~ = w - F_Aw and
+// u -= F_ww.  With the cotangent Fbar of F (symmetric) and dbar = -1/2,
+//   Xbar = 2 P^{-1} X Fbar = 2 V Fbar,  Pbar = -V Fbar V' - 1/2 P^{-1},
+// V = P^{-1} X = L^{-T} (L^{-1} X), which only needs the stored factors.
+// At a region the outputs are A - F_AA, w - F_Aw and u - F_ww, so
+// Fbar = [[-S, -wbar/2], [-wbar'/2, 1/2]]; at a leaf they are F itself
+// (A~ = F_AA, w~ = F_Az, u = F_zz), so Fbar = [[S, wbar/2], [wbar'/2, -1/2]].
+// S is the symmetric form of the cotangent of the parent's A (off-diagonal
+// blocks halved); every region inherits its parent's cotangents for the
+// blocks k, l < m, so the cotangent of A^{k,l} below region a_k is the one
+// stored at a_k (row k).
+//
+// The prior recursion (eq. priorw, whitened) is reversed row by row:
+// W^^l = W^l L_{a_l}^{-T} gives Wbar^l = W^^bar^l L_{a_l}^{-1} and
+// L_{a_l}-bar = -tril(sum_rows Wbar^l' W^^l); the ancestors' cotangents are
+// subtree sums Tsum^{l,k} = sum over rows of Wbar^l' W^^k, accumulated with
+// the child sums of the tree (no atomics); L_R = chol(W^m_R) is reversed by
+// the Cholesky adjoint Wbar^m = sym(L^{-T} Phi(L' Lbar) L^{-1}).  Every
+// covariance entry's cotangent Cbar is contracted with dC/dlog sigma^2 = C
+// and dC/dlog kappa; dloglik/dlog tau^2 = tau^2 tr(Sigma-bar) over the leaves.
+#include "common.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
 namespace mra {
 
+// acc += alpha * V * S^{k,c} with S from the cotangents stored at the
+// ancestors a_k, a_c of a region at level `lev`, index `idx`
+__device__ void gemm_S(Acc& acc, const DevPlan& P, double* S, const double* V, int k, int c, int lev, int64_t idx,
+                       double alpha, double* lds) {
+  if (k > c) {
+    Grad g = grad_of(P, S, k, ancestor(P, lev, idx, k));
+    gemm<Op::N, Op::N>(acc, V, T, g.G(c), T, T, 0.5 * alpha, lds);
+  } else if (k < c) {
+    Grad g = grad_of(P, S, c, ancestor(P, lev, idx, c));
+    gemm<Op::N, Op::T>(acc, V, T, g.G(k), T, T, 0.5 * alpha, lds);
+  } else {
+    Grad g = grad_of(P, S, k, ancestor(P, lev, idx, k));
+    gemm<Op::N, Op::N>(acc, V, T, g.G(k), T, T, alpha, lds);
+  }
+}
+
+__device__ __forceinline__ const double* wbar_omega_of(const DevPlan& P, double* S, int k, int lev, int64_t idx) {
+  return grad_of(P, S, k, ancestor(P, lev, idx, k)).wbar_omega();
+}
+
+// symmetrise a tile in global memory in place (tile written by this block)
+__device__ void symmetrize(double* C) {
+  __syncthreads();
+  double v[TT / NT];
+  for (int q = 0; q < TT / NT; ++q) {
+    int e = threadIdx.x + q * NT, i = e >> 6, j = e & 63;
+    v[q] = 0.5 * (C[i * T + j] + C[j * T + i]);
+  }
+  __syncthreads();
+  for (int q = 0; q < TT / NT; ++q) C[threadIdx.x + q * NT] = v[q];
+  __syncthreads();
+}
+
+__device__ void write_partial(const DevPlan& P, double* S, int64_t slot, double g[3], double* red) {
+  double a = block_sum(g[0], red);
+  double b = block_sum(g[1], red);
+  double c = block_sum(g[2], red);
+  if (threadIdx.x == 0) {
+    double* o = S + P.off_gpart + slot * 4;
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+    o[3] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- posterior
+// region (m, i), top-down: G^{m,l} = Xbar_l, G^{m,m} = Pbar, wbar^m = xbar_w
+__global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int64_t i = i0 + blockIdx.x;
+  double* S = slice(P, th);
+  Post po = post_of(P, S, m, i);
+  Grad gr = grad_of(P, S, m, i);
+  double* vw = gr.scratch();          // v_w = Lt^{-T} z_w (first T entries of the scratch tile)
+  Acc acc;
+  for (int l = 0; l < m; ++l) {       // V_l = Lt^{-T} Z_l, kept in the Tsum tiles (free until later)
+    acc_zero(acc);
+    gemm<Op::T, Op::N>(acc, po.Lti(), T, po.Z(l), T, T, 1.0, lds);
+    acc_store(acc, gr.Tsum(0, 0) + (int64_t)l * TT, T);
+  }
+  if (threadIdx.x < T) {
+    double s = 0.0;
+    const double* Li = po.Lti();
+    const double* zw = po.zw();
+    for (int q = threadIdx.x; q < T; ++q) s += Li[q * T + threadIdx.x] * zw[q];
+    vw[threadIdx.x] = s;
+  }
+  __syncthreads();
+  const double* V0 = gr.Tsum(0, 0);
+  for (int l = 0; l < m; ++l) {       // Xbar_l = -2 sum_k V_k S^{k,l} - v_w wbar^l'
+    acc_zero(acc);
+    for (int k = 0; k < m; ++k) gemm_S(acc, P, S, V0 + (int64_t)k * TT, k, l, m, i, -2.0, lds);
+    const double* wb = wbar_omega_of(P, S, l, m, i);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] -= vw[acc_row(bi, v)] * wb[acc_col(bj)];
+    acc_store(acc, gr.G(l), T);
+  }
+  if (threadIdx.x < T) {              // xbar_w = -sum_k V_k wbar^k + v_w
+    double s = vw[threadIdx.x];
+    for (int k = 0; k < m; ++k) {
+      const double* Vk = V0 + (int64_t)k * TT + threadIdx.x * T;
+      const double* wb = wbar_omega_of(P, S, k, m, i);
+      for (int j = 0; j < T; ++j) s -= Vk[j] * wb[j];
+    }
+    gr.wbar_omega()[threadIdx.x] = s;
+  }
+  __syncthreads();
+  // Pbar = -1/2 (sum_l Xbar_l V_l' + xbar_w v_w' + Lt^{-T} Lt^{-1})
+  acc_zero(acc);
+  for (int l = 0; l < m; ++l) gemm<Op::N, Op::T>(acc, gr.G(l), T, V0 + (int64_t)l * TT, T, T, -0.5, lds);
+  gemm<Op::T, Op::N>(acc, po.Lti(), T, po.Lti(), T, T, -0.5, lds);
+  const double* xw = gr.wbar_omega();
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] -= 0.5 * xw[acc_row(bi, v)] * vw[acc_col(bj)];
+  acc_store(acc, gr.G(m), T);
+  symmetrize(gr.G(m));
+}
+
+// ---------------------------------------------------------------- leaves
+// V = L_Sigma^{-T} Y for one column plane (backward substitution by tiles)
+__global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int32_t* task = P.trsm_tasks + 2 * (t0 + blockIdx.x);
+  const int leaf = task[0], cpl = task[1];
+  double* S = slice(P, th);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const double* base = S + P.off_sig + P.leaf_soff[leaf] * TT;
+  const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
+  const double* Y = S + P.off_y + cpl * P.plane + poff * T;
+  double* V = S + P.off_v + cpl * P.plane + poff * T;
+  Acc acc;
+  for (int ib = nb - 1; ib >= 0; --ib) {
+    acc_load(acc, Y + (int64_t)ib * TT, T);
+    for (int jb = ib + 1; jb < nb; ++jb)
+      gemm<Op::T, Op::N>(acc, base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, T, -1.0, lds);
+    acc_store(acc, V + (int64_t)ib * TT, T);
+    __syncthreads();
+    acc_zero(acc);
+    gemm<Op::T, Op::N>(acc, dinv + (int64_t)ib * TT, T, V + (int64_t)ib * TT, T, T, 1.0, lds);
+    acc_store(acc, V + (int64_t)ib * TT, T);
+    __syncthreads();
+  }
+}
+
+// tile column j of L_Sigma^{-1} (forward substitution of the identity)
+__global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int32_t* task = P.linv_tasks + 2 * (t0 + blockIdx.x);
+  const int leaf = task[0], j = task[1];
+  double* S = slice(P, th);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const double* base = S + P.off_sig + P.leaf_soff[leaf] * TT;
+  const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
+  double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
+  Acc acc;
+  acc_load(acc, dinv + (int64_t)j * TT, T);
+  acc_store(acc, Li + ((int64_t)j * nb + j) * TT, T);
+  __syncthreads();
+  for (int ib = j + 1; ib < nb; ++ib) {
+    acc_zero(acc);
+    for (int kb = j; kb < ib; ++kb)
+      gemm<Op::N, Op::N>(acc, base + ((int64_t)ib * nb + kb) * TT, T, Li + ((int64_t)kb * nb + j) * TT, T, T, -1.0,
+                         lds);
+    double* out = Li + ((int64_t)ib * nb + j) * TT;
+    acc_store(acc, out, T);
+    __syncthreads();
+    acc_zero(acc);
+    gemm<Op::N, Op::N>(acc, dinv + (int64_t)ib * TT, T, out, T, T, 1.0, lds);
+    acc_store(acc, out, T);
+    __syncthreads();
+  }
+}
+
+// Q = V Fbar for one 64-row tile and one column plane c (c = M: the z column)
+__global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int M = P.M;
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t tsk = gid / (M + 1);
+  const int c = (int)(gid % (M + 1));
+  const int32_t* task = P.row_tasks + 2 * tsk;
+  const int leaf = task[0];
+  const int64_t p0 = task[1];
+  double* S = slice(P, th);
+  const double* V = S + P.off_v + p0 * T;
+  const double* vz = S + P.off_v + (int64_t)M * P.plane + p0 * T;   // column 0
+  double* Q = S + P.off_q + (int64_t)c * P.plane + p0 * T;
+  if (c < M) {
+    Acc acc;
+    acc_zero(acc);
+    for (int k = 0; k < M; ++k) gemm_S(acc, P, S, V + (int64_t)k * P.plane, k, c, M, leaf, 1.0, lds);
+    const double* wb = wbar_omega_of(P, S, c, M, leaf);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] += 0.5 * vz[acc_row(bi, v) * T] * wb[acc_col(bj)];
+    acc_store(acc, Q, T);
+  } else {
+    // q_z = 1/2 sum_k V_k wbar^k - 1/2 v_z in column 0, zero elsewhere
+    for (int e = threadIdx.x; e < TT; e += NT) {
+      int r = e >> 6, col = e & 63;
+      double s = 0.0;
+      if (col == 0) {
+        s = -0.5 * vz[r * T];
+        for (int k = 0; k < M; ++k) {
+          const double* Vk = V + (int64_t)k * P.plane + r * T;
+          const double* wb = wbar_omega_of(P, S, k, M, leaf);
+          double t = 0.0;
+          for (int j = 0; j < T; ++j) t += Vk[j] * wb[j];
+          s += 0.5 * t;
+        }
+      }
+      Q[e] = s;
+    }
+  }
+}
+
+// Sigma-bar tile (bi, bj) = -sum_c Q_c[bi] V_c[bj]' - 1/2 (Sigma^{-1})_{bi,bj},
+// contracted with the leaf covariance tile
+__global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* theta, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int64_t tk = t0 + blockIdx.x;
+  const int32_t* task = P.sig_tasks + 3 * tk;
+  const int leaf = task[0], bi = task[1], bj = task[2];
+  double* S = slice(P, th);
+  const CovP cp = load_cov(theta + 3 * th, P.cov);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const int nR = P.leaf_n[leaf];
+  const int64_t pi = poff + (int64_t)T * bi, pj = poff + (int64_t)T * bj;
+  const double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
+  Acc acc;
+  acc_zero(acc);
+  for (int c = 0; c <= P.M; ++c)
+    gemm<Op::N, Op::T>(acc, S + P.off_q + c * P.plane + pi * T, T, S + P.off_v + c * P.plane + pj * T, T, T, -1.0,
+                       lds);
+  for (int kb = bi; kb < nb; ++kb)
+    gemm<Op::T, Op::N>(acc, Li + ((int64_t)kb * nb + bi) * TT, T, Li + ((int64_t)kb * nb + bj) * TT, T, T, -0.5, lds);
+  double* out = S + P.off_sbar + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT;
+  acc_store(acc, out, T);
+  if (bi == bj) {
+    symmetrize(out);
+    acc_load(acc, out, T);
+  }
+  double g[3] = {0.0, 0.0, 0.0};
+  acc_cov_contract(acc, P.obs_xy + 2 * pi, min(T, nR - T * bi), P.obs_xy + 2 * pj, min(T, nR - T * bj), cp,
+                   bi == bj, g);
+  const double wgt = (bi == bj) ? 1.0 : 2.0;   // lower tiles stand for both triangles
+  g[0] *= wgt;
+  g[1] *= wgt;
+  write_partial(P, S, tk, g, red);
+}
+
+// W^-bar of the leaf rows: 2 Q_c - 2 Sigma-bar W^_c, per row tile and plane c < M
+__global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int M = P.M;
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t tsk = gid / M;
+  const int c = (int)(gid % M);
+  const int32_t* task = P.row_tasks + 2 * tsk;
+  const int leaf = task[0];
+  const int64_t p0 = task[1];
+  double* S = slice(P, th);
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const int bi = (int)((p0 - poff) / T);
+  const double* Sb = S + P.off_sbar + P.leaf_soff[leaf] * TT;
+  const double* W = S + P.off_wobs + (int64_t)c * P.plane + poff * T;
+  Acc acc;
+  acc_load(acc, S + P.off_q + (int64_t)c * P.plane + p0 * T, T);
+#pragma unroll
+  for (int bi2 = 0; bi2 < 2; ++bi2)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc.c[bi2][bj] *= 2.0;
+  for (int bj = 0; bj < nb; ++bj) {
+    if (bj <= bi)
+      gemm<Op::N, Op::N>(acc, Sb + ((int64_t)bi * nb + bj) * TT, T, W + (int64_t)bj * TT, T, T, -2.0, lds);
+    else
+      gemm<Op::T, Op::N>(acc, Sb + ((int64_t)bj * nb + bi) * TT, T, W + (int64_t)bj * TT, T, T, -2.0, lds);
+  }
+  acc_store(acc, S + P.off_wbar + (int64_t)c * P.plane + p0 * T, T);
+}
+
+// Reverse row sweep for 64 rows (points X, nx valid) of a region at level
+// lev: Wbar^l = W^-bar^l L_{a_l}^{-1}, contracted with C_0(X, Q_{a_l});
+// W^-bar^k -= Wbar^l W^^k_{a_l}.  rows + l*bstride hold W^-bar, then Wbar.
+__device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
+                                  int64_t bstride, int lev, int64_t idx, double g[3], double* lds) {
+  Acc acc;
+  for (int l = lev - 1; l >= 0; --l) {
+    const int64_t al = ancestor(P, lev, idx, l);
+    const double* Pa = prior_reg(P, S, l, al);
+    double* Rl = rows + l * bstride;
+    acc_zero(acc);
+    gemm<Op::N, Op::N>(acc, Rl, T, Pa + (l + 1) * TT, T, T, 1.0, lds);
+    acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
+    acc_store(acc, Rl, T);
+    __syncthreads();
+    for (int k = 0; k < l; ++k) {
+      double* Rk = rows + k * bstride;
+      acc_load(acc, Rk, T);
+      gemm<Op::N, Op::N>(acc, Rl, T, Pa + (int64_t)k * TT, T, T, -1.0, lds);
+      acc_store(acc, Rk, T);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rrows_leaf(DevPlan P, const double* theta, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int64_t tk = t0 + blockIdx.x;
+  const int32_t* task = P.row_tasks + 2 * tk;
+  const int leaf = task[0];
+  const int64_t p0 = task[1];
+  double* S = slice(P, th);
+  const CovP c = load_cov(theta + 3 * th, P.cov);
+  const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
+  double g[3] = {0.0, 0.0, 0.0};
+  row_sweep_reverse(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wbar + p0 * T, P.plane, P.M, leaf, g, lds);
+  write_partial(P, S, P.n_sig_tasks + tk, g, red);
+}
+
+// Tsum^{l,k} of a level-(M-1) region: sum over its leaves' rows of Wbar^l' W^^k
+__global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int M = P.M;
+  const int nkl = M * (M + 1) / 2;
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t pidx = gid / nkl;
+  int l, k;
+  kl_split((int)(gid % nkl), l, k);
+  double* S = slice(P, th);
+  const double* Wb = S + P.off_wbar + (int64_t)l * P.plane;
+  const double* Wh = S + P.off_wobs + (int64_t)k * P.plane;
+  Acc acc;
+  acc_zero(acc);
+  for (int cc = 0; cc < P.J; ++cc) {
+    const int64_t leaf = pidx * P.J + cc;
+    for (int64_t p = P.leaf_poff[leaf]; p < P.leaf_poff[leaf + 1]; p += T)
+      gemm<Op::T, Op::N>(acc, Wb + p * T, T, Wh + p * T, T, T, 1.0, lds);
+  }
+  acc_store(acc, grad_of(P, S, M - 1, pidx).Tsum(l, k), T);
+}
+
+// ---------------------------------------------------------------- prior
+// region (m, i), bottom-up: Cholesky adjoint of L_R, then the reverse row
+// sweep of its knots
+__global__ __launch_bounds__(NT) void k_rprior(DevPlan P, const double* theta, int m, int64_t i0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double red[8];
+  const int th = blockIdx.y;
+  const int64_t i = i0 + blockIdx.x;
+  double* S = slice(P, th);
+  const CovP c = load_cov(theta + 3 * th, P.cov);
+  Grad gr = grad_of(P, S, m, i);
+  double* reg = prior_reg(P, S, m, i);
+  const double* L = reg + (int64_t)m * TT;
+  const double* Li = reg + (int64_t)(m + 1) * TT;
+  double* sc = gr.scratch();
+  const double* X = knots_of(P, m, i);
+  // Lbar = -tril(Tsum^{m,m})
+  const double* Tmm = gr.Tsum(m, m);
+  for (int e = threadIdx.x; e < TT; e += NT) {
+    int r = e >> 6, q = e & 63;
+    sc[e] = (q <= r) ? -Tmm[e] : 0.0;
+  }
+  __syncthreads();
+  Acc acc;
+  acc_zero(acc);
+  gemm<Op::T, Op::N>(acc, L, T, sc, T, T, 1.0, lds);     // L' Lbar
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = acc_row(bi, v), q = acc_col(bj);
+        if (q > r) acc.c[bi][bj][v] = 0.0;
+        else if (q == r) acc.c[bi][bj][v] *= 0.5;       // Phi
+      }
+  acc_store(acc, sc, T);
+  __syncthreads();
+  acc_zero(acc);
+  gemm<Op::N, Op::N>(acc, sc, T, Li, T, T, 1.0, lds);    // Phi L^{-1}
+  acc_store(acc, sc, T);
+  __syncthreads();
+  acc_zero(acc);
+  gemm<Op::T, Op::N>(acc, Li, T, sc, T, T, 1.0, lds);    // L^{-T} Phi L^{-1}
+  acc_store(acc, sc, T);
+  symmetrize(sc);                                        // Wbar^m
+  acc_load(acc, sc, T);
+  double g[3] = {0.0, 0.0, 0.0};
+  acc_cov_contract(acc, X, P.r, X, P.r, c, false, g);
+  // W^-bar^k = -Tsum^{m,k} - 2 Wbar^m W^^k_R, k < m
+  for (int k = 0; k < m; ++k) {
+    acc_load(acc, gr.Tsum(m, k), T);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc.c[bi][bj] = -acc.c[bi][bj];
+    gemm<Op::N, Op::N>(acc, sc, T, reg + (int64_t)k * TT, T, T, -2.0, lds);
+    acc_store(acc, gr.Wbar(k), T);
+  }
+  __syncthreads();
+  row_sweep_reverse(P, S, c, X, P.r, gr.Wbar(0), TT, m, i, g, lds);
+  write_partial(P, S, P.n_sig_tasks + P.n_row_tasks + P.reg_base[m] + i, g, red);
+}
+
+// Tsum of a level-(m-1) region: sum over children (level m) of
+// Tsum_c^{l,k} + Wbar_c^l' W^^k_c, k <= l <= m-1
+__global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, int64_t t0) {
+  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  const int th = blockIdx.y;
+  const int nkl = m * (m + 1) / 2;
+  const int64_t gid = t0 + blockIdx.x;
+  const int64_t pidx = gid / nkl;
+  int l, k;
+  kl_split((int)(gid % nkl), l, k);
+  double* S = slice(P, th);
+  Acc acc;
+  acc_zero(acc);
+  for (int cc = 0; cc < P.J; ++cc) {
+    const int64_t ch = pidx * P.J + cc;
+    Grad gc = grad_of(P, S, m, ch);
+    acc_load(acc, gc.Tsum(l, k), T, true);
+    gemm<Op::T, Op::N>(acc, gc.Wbar(l), T, prior_reg(P, S, m, ch) + (int64_t)k * TT, T, T, 1.0, lds);
+  }
+  acc_store(acc, grad_of(P, S, m - 1, pidx).Tsum(l, k), T);
+}
+
+// sum of the partials in a fixed order: grad = (sum g0, sum g1, tau^2 sum g2)
+__global__ __launch_bounds__(NT) void k_gsum(DevPlan P, const double* theta, double* out, int64_t nslot) {
+  __shared__ double red[8];
+  const int th = blockIdx.x;
+  double* S = slice(P, th);
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t q = threadIdx.x; q < nslot; q += NT) {
+    const double* o = S + P.off_gpart + q * 4;
+    a += o[0];
+    b += o[1];
+    c += o[2];
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    const double tau2 = exp(theta[3 * th + 2]);
+    const bool bad = *(const unsigned long long*)(S + P.off_status) != 0ull;
+    const double nan = __builtin_nan("");
+    out[3 * th + 0] = bad ? nan : a;
+    out[3 * th + 1] = bad ? nan : b;
+    out[3 * th + 2] = bad ? nan : tau2 * c;
+  }
+}
+
+__global__ void k_zero_gpart(DevPlan P, int64_t nslot) {
+  double* S = slice(P, blockIdx.y);
+  for (int64_t q = blockIdx.x * (int64_t)NT + threadIdx.x; q < nslot * 4; q += (int64_t)gridDim.x * NT)
+    S[P.off_gpart + q] = 0.0;
+}
+
 hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st) {
-  (void)H; (void)theta; (void)nth; (void)out_grad; (void)st;
-  return hipErrorNotSupported;
+  const DevPlan& P = H.dp;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0};
+  const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
+  const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
+  hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
+  for (int m = 0; m < M; ++m) run(k_rpost, P.nreg[m], m);
+  run(k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
+  run(k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
+  run(k_rleaf_q, nrow * (M + 1));
+  run(k_rleaf_sbar, P.n_sig_tasks, theta);
+  if (M > 0) {
+    run(k_rleaf_wbar, nrow * M);
+    run(k_rrows_leaf, nrow, theta);
+    run(k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    for (int m = M - 1; m >= 0; --m) {
+      run(k_rprior, P.nreg[m], theta, m);
+      if (m > 0) run(k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+    }
+  }
+  hipLaunchKernelGGL(k_gsum, dim3(nth), dim3(NT), 0, st, P, theta, out_grad, nslot);
+  return hipGetLastError();
 }
 
 }  // namespace mra

@@ -201,7 +201,8 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return P->leaf_n[x] > P->leaf_n[y]; });
-  P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->pred_tasks.clear();
+  P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->linv_tasks.clear();
+  P->pred_tasks.clear();
   for (int32_t i : order) {
     int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
     if (nb == 0) continue;
@@ -212,6 +213,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
         P->sig_tasks.push_back(i); P->sig_tasks.push_back((int32_t)bi); P->sig_tasks.push_back((int32_t)bj);
       }
     for (int c = 0; c <= M; ++c) { P->trsm_tasks.push_back(i); P->trsm_tasks.push_back(c); }
+    for (int64_t j = 0; j < nb; ++j) { P->linv_tasks.push_back(i); P->linv_tasks.push_back((int32_t)j); }
   }
   for (int64_t i = 0; i < n_leaves; ++i) {
     int64_t nb = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;
@@ -236,16 +238,20 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.g_sigt = take(std::max<size_t>(P->sig_tasks.size(), 1) * 4);
   L.g_fact = take(std::max<size_t>(P->fac_tasks.size(), 1) * 4);
   L.g_trst = take(std::max<size_t>(P->trsm_tasks.size(), 1) * 4);
+  L.g_lint = take(std::max<size_t>(P->linv_tasks.size(), 1) * 4);
   L.g_pxy = take(P->pred_xy.size() * 8);
   L.g_pgidx = take(P->pred_gidx.size() * 8);
   L.g_pt = take(std::max<size_t>(P->pred_tasks.size(), 1) * 4);
   L.g_pleafn = take(P->pleaf_n.size() * 4);
+  L.g_ppoff = take(P->pleaf_poff.size() * 8);
   L.geom_bytes = off;
 
   // ---- work arena layout (doubles per theta slice) ----
   DevPlan& D = P->dp;
   D = DevPlan{};
   D.d = d; D.M = M; D.J = J; D.r = r; D.cov = cfg->cov;
+  D.n_sig_tasks = (int64_t)P->sig_tasks.size() / 3;
+  D.n_row_tasks = (int64_t)P->row_tasks.size() / 2;
   D.n = n; D.npad = P->npad; D.n_leaves = n_leaves; D.ppad = P->ppad; D.n_pred = n_pred;
   int64_t w = 0;
   auto wtake = [&](int64_t doubles) { int64_t o = w; w = round_up(w + doubles, 32); return o; };
@@ -275,12 +281,17 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   D.off_v = wtake((M + 1) * D.plane);
   D.off_q = wtake((M + 1) * D.plane);
   D.off_sbar = wtake(P->n_sig_tiles * TT);
+  D.off_linv = wtake(P->n_sig_tiles * TT);
   D.off_wbar = wtake(std::max(M, 1) * D.plane);
   // gradient partial sums: one slot per task of every gradient-producing launch
   D.n_gpart = (int64_t)P->sig_tasks.size() / 3 + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
   D.off_gpart = wtake(D.n_gpart * 4);
   D.off_pw = wtake(std::max(M, 1) * P->ppad * T);
-  D.off_pl = 0;
+  int64_t nbmax = 1;
+  for (int64_t i = 0; i < n_leaves; ++i)
+    if (P->pleaf_n[i] > 0) nbmax = std::max<int64_t>(nbmax, (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T);
+  D.pl_stride = nbmax * TT;
+  D.off_pl = wtake(std::max<int64_t>((int64_t)P->pred_tasks.size() / 2, 1) * D.pl_stride);
   D.theta_stride = w;
   L.theta_stride = w;
 

@@ -15,8 +15,8 @@ struct GraphCache;  // defined in api.cpp
 
 struct Layout {
   // geometry arena (byte offsets)
-  size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst;
-  size_t g_pxy, g_pgidx, g_pt, g_pleafn, geom_bytes;
+  size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst, g_lint;
+  size_t g_pxy, g_pgidx, g_pt, g_pleafn, g_ppoff, geom_bytes;
   // work arena (doubles per theta slice)
   int64_t theta_stride;
 };
@@ -45,7 +45,7 @@ struct mra_plan_s {
   std::vector<double> pred_xy;
   std::vector<int64_t> pred_gidx;
   // task lists
-  std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, pred_tasks;
+  std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, linv_tasks, pred_tasks;
   // layout
   mra::Layout lay;
   mra::DevPlan dp;

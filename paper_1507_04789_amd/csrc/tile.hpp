@@ -2,8 +2,10 @@
 // wave64s) owns one 64x64 output tile; each wave owns a 32x32 quadrant held
 // as 2x2 accumulators of v_mfma_f64_16x16x4_f64.
 //
-// Accumulator layout (per lane l of wave w, accumulator (bi, bj), item v):
-//   row = 32*(w>>1) + 16*bi + 4*(l>>4) + v,   col = 32*(w&1) + 16*bj + (l&15)
+// Accumulator layout (per lane l of wave w, accumulator (bi, bj), item v),
+// as measured on gfx950 (item v of lane l holds row 4*v + l/16 of the 16x16
+// block, column l%16):
+//   row = 32*(w>>1) + 16*bi + 4*v + (l>>4),   col = 32*(w&1) + 16*bj + (l&15)
 // MFMA operand layout for 16x16x4: lane l supplies A[l&15][l>>4] and
 // B[l>>4][l&15].
 //
@@ -31,7 +33,7 @@ struct Acc {
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int acc_row(int bi, int v) {
-  return 32 * (wave_id() >> 1) + 16 * bi + 4 * (lane_id() >> 4) + v;
+  return 32 * (wave_id() >> 1) + 16 * bi + 4 * v + (lane_id() >> 4);
 }
 __device__ __forceinline__ int acc_col(int bj) { return 32 * (wave_id() & 1) + 16 * bj + (lane_id() & 15); }
 

@@ -1,0 +1,69 @@
+"""GPU parity of the kriging pass (Prop. 2) against the oracle: posterior
+predictive mean and marginal variance of the latent process, relative error
+<= 1e-10 (variances compared relative to sigma^2, the prior variance)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import predict
+from oracle.geometry import Geometry
+from paper_1507_04789_amd import Plan
+from paper_1507_04789_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _th(s2, k, t2):
+    return np.array([math.log(s2), math.log(k), math.log(t2)])
+
+
+def _case(locs, z, pred, kind, th, M, J, r, d=2, knots=None):
+    print("predict case n=%d np=%d M=%d J=%d r=%d d=%d %s" % (len(z), len(pred), M, J, r, d, kind), flush=True)
+    p = Plan(locs, M=M, J=J, r=r, cov=kind, d=d, knots=knots, pred=pred)
+    mu, var = p.predict(z, th)
+    mu, var = mu.cpu().numpy(), var.cpu().numpy()
+    geo = Geometry(locs, d, M, J, r, knots=knots)
+    rmu, rvar = predict.predict(geo, z, kind, th, pred)
+    s2 = math.exp(th[0])
+    scale = max(np.abs(rmu).max(), 1e-300)
+    assert np.abs(mu - rmu).max() <= 1e-10 * scale, np.abs(mu - rmu).max() / scale
+    assert np.abs(var - rvar).max() <= 1e-10 * s2, np.abs(var - rvar).max() / s2
+    assert (var > 0).all()
+
+
+def test_predict_uniform_exponential_m3_r16():
+    w = wl.small_uniform()
+    _case(w.locs, w.z, w.pred, w.cov, w.theta, w.M, w.J, w.r)
+
+
+@pytest.mark.parametrize("M,r", [(0, 16), (1, 16), (2, 9)])
+def test_predict_small(M, r):
+    g = np.random.default_rng(20 + M)
+    locs = g.random((900, 2))
+    z = g.standard_normal(900)
+    pred = g.random((300, 2))
+    _case(locs, z, pred, "matern32", _th(1.1, 0.12, 0.02), M, 4, r)
+
+
+def test_predict_empty_leaves_and_large_leaf():
+    g = np.random.default_rng(6)
+    locs = np.concatenate([g.random((500, 2)) * 0.25, g.random((30, 2)) * 0.5 + 0.5])
+    z = g.standard_normal(locs.shape[0])
+    pred = g.random((400, 2))            # many fall in empty leaves
+    _case(locs, z, pred, "matern32", _th(1.0, 0.1, 0.01), 3, 4, 16)
+
+
+def test_predict_clustered_r64():
+    w = wl.clustered(n=16384, M=4)
+    pred = np.random.default_rng(3).random((2000, 2))
+    _case(w.locs, w.z, pred, w.cov, w.theta, w.M, w.J, w.r)
+
+
+def test_predict_one_dimensional_exact():
+    g = np.random.default_rng(7)
+    locs = g.random((300, 1))
+    z = g.standard_normal(300)
+    pred = g.random((100, 1))
+    _case(locs, z, pred, "exponential", _th(1.0, 0.3, 0.05), 5, 2, 1, d=1)
