@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the M-RA FP64 log-likelihood + gradient on one MI355X.
+
+Workload: n = 2^18 locations (half uniform, half in 200 Gaussian clusters of
+sd 0.01) on the unit square, Matern nu = 1.5 with sigma^2 = 1, kappa = 0.1,
+tau^2 = 0.01; M = 6 levels of quadrant splits (4096 leaves of uneven size),
+r = 64 knots per region.  One step is one log-likelihood plus its reverse-
+pass gradient in (log sigma^2, log kappa, log tau^2), with the data resident
+in HBM.  Printed as one JSON line; see --help.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+METRIC = "M-RA loglik+grad evals/s at n=2^18 (batched vs plain, 1 GPU); FP64 MFMA % peak"
+
+
+def _dominant(stats):
+    """Aggregate per-kernel records over levels; pick the kernel with the
+    largest summed time."""
+    fam = {}
+    for s in stats:
+        f = fam.setdefault(s["name"], {"name": s["name"], "groups": 0, "launches": 0, "total_ms": 0.0, "flops": 0.0})
+        for k in ("groups", "launches", "total_ms", "flops"):
+            f[k] += s[k]
+    ranked = sorted(fam.values(), key=lambda f: -f["total_ms"])
+    return ranked
+
+
+def cpu_baseline(sample_n: int, sample_M: int, full_flops: float):
+    """The oracle, single-threaded, on a bounded sample of the same workload
+    family; throughput scaled to the full workload by the algorithmic flop
+    ratio."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mra
+    from oracle.geometry import Geometry
+    from paper_1507_04789_amd import Plan
+    from paper_1507_04789_amd import workloads as wl
+    w = wl.clustered(n=sample_n, M=sample_M)
+    sp = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov)
+    with threadpool_limits(1):
+        geo = Geometry(w.locs, 2, w.M, w.J, w.r)
+        t0 = time.perf_counter()
+        mra.loglik(geo, w.z, w.cov, w.theta, grad=True)
+        dt = time.perf_counter() - t0
+    ratio = sp.info["flops_grad"] / full_flops
+    return {"value": ratio / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle loglik + forward-mode gradient on the same generator at n=%d, M=%d (64 obs/leaf "
+                      "on average, as the full workload), %.2f s single-threaded, scaled by the algorithmic "
+                      "flop ratio %.4g" % (sample_n, sample_M, dt, ratio),
+            "cpu": _cpu_name()}
+
+
+def _cpu_name():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--M", type=int, default=6)
+    ap.add_argument("--plain-steps", type=int, default=2, help="steps of the one-launch-per-task form (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the M-RA path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_04789_amd import Plan
+    from paper_1507_04789_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    w = wl.clustered(n=args.n, M=args.M)
+    plan = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=0)
+    plan.bind(dev)
+    z = torch.tensor(w.z, device=dev)
+    th = torch.tensor(w.theta, device=dev).reshape(1, 3)
+    flops = plan.info["flops_grad"]
+
+    for _ in range(args.warmup):
+        ll, g = plan.loglik_grad(z, th)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        ll, g = plan.loglik_grad(z, th)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    stats = plan.profile_read()
+    plan.profile(False)
+    llv, gv = float(ll[0]), g[0].tolist()
+    if not (math.isfinite(llv) and all(math.isfinite(x) for x in gv)):
+        raise RuntimeError("non-finite result: loglik %r grad %r" % (llv, gv))
+    fam = _dominant(stats)
+    dom = fam[0]
+    per_launch_flops = dom["flops"] / dom["groups"]
+    avg_ms = dom["total_ms"] / dom["groups"]
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+
+    plain = None
+    if args.plain_steps > 0:
+        pplan = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=2)
+        pplan.bind(dev)
+        pplan.loglik_grad(z, th)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record()
+        for _ in range(args.plain_steps):
+            pll, pg = pplan.loglik_grad(z, th)
+        p1.record()
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1) / args.plain_steps
+        plain = {"value": 1000.0 / pms, "ms_per_step": pms, "steps": args.plain_steps,
+                 "same_result": bool(float(pll[0]) == llv and pg[0].tolist() == gv)}
+        del pplan
+        torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "clustered_n%d_matern32_M%d_J4_r64_loglik_grad" % (args.n, args.M),
+                   "n": args.n, "M": args.M, "J": 4, "r": 64, "cov": "matern32",
+                   "theta": {"sigma2": 1.0, "kappa": 0.1, "tau2": 0.01}, "batch_theta": 1},
+        "fp64_pct_peak_step": 100.0 * flops / (ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
+        "algorithmic_flops_per_step": flops,
+        "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "flops_per_launch": per_launch_flops, "avg_launch_ms": avg_ms},
+        "kernels": [{"name": f["name"], "ms_per_step": f["total_ms"] / args.steps,
+                     "tflops": (f["flops"] / (f["total_ms"] * 1e-3) / 1e12) if f["total_ms"] > 0 else None}
+                    for f in fam[:8]],
+        "plain": plain,
+        "result": {"loglik": llv, "grad": gv},
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(16384, max(args.M - 2, 1), flops)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,24 @@ mra_status mra_predict(mra_plan_t plan, const double* d_y, const double* d_theta
 mra_status mra_last_failure(mra_plan_t plan, int32_t* theta_idx, int32_t* level,
                             int64_t* region, void* stream);
 
+/* Per-kernel timing (tracing).  mra_profile(plan, 1) enables HIP-event
+ * timing of every launch group of the following calls on their streams and
+ * clears earlier records; mra_profile(plan, 0) disables it.
+ * mra_profile_read synchronises `stream`, aggregates the records by
+ * (kernel, level) into out[0..cap), sets *count to the number of distinct
+ * entries (which may exceed cap) and clears the records. */
+typedef struct {
+  char name[24];      /* kernel family, e.g. "leaf_reduce" */
+  int32_t level;      /* tree level for per-level kernels, -1 otherwise */
+  int64_t groups;     /* timed launch groups */
+  int64_t launches;   /* kernel launches (one per task in the plain form) */
+  double total_ms;    /* summed event time of the groups */
+  double flops;       /* summed algorithmic FP64 flops of the groups */
+} mra_phase_stat;
+
+mra_status mra_profile(mra_plan_t plan, int32_t enable);
+mra_status mra_profile_read(mra_plan_t plan, mra_phase_stat* out, int32_t cap, int32_t* count, void* stream);
+
 const char* mra_status_string(mra_status s);
 
 /* Release the plan (and any captured graphs).  Does not free the arenas. */

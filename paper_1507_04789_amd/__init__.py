@@ -166,6 +166,22 @@ class Plan:
         self._fail(s, "mra_predict")
         return mean, var
 
+    # -- tracing ----------------------------------------------------------------
+    def profile(self, enable: bool = True):
+        """Enable (and clear) or disable per-kernel HIP-event timing."""
+        _lib.check(_lib.lib().mra_profile(self._h, 1 if enable else 0), "mra_profile")
+
+    def profile_read(self):
+        """Aggregated per-kernel timings since the last read:
+        list of dicts (name, level, groups, launches, total_ms, flops)."""
+        cap = 256
+        buf = (_lib.PhaseStat * cap)()
+        cnt = C.c_int32()
+        st = self._stream() if self.device is not None else None
+        _lib.check(_lib.lib().mra_profile_read(self._h, buf, cap, C.byref(cnt), st), "mra_profile_read")
+        return [{"name": b.name.decode(), "level": b.level, "groups": b.groups, "launches": b.launches,
+                 "total_ms": b.total_ms, "flops": b.flops} for b in buf[:min(cnt.value, cap)]]
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib._lib is not None:

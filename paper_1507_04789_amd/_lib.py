@@ -13,7 +13,8 @@ MRA_SYNC, MRA_PLAIN, MRA_GRAPH = 1, 2, 4
 
 # every symbol the header declares
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",
-           "mra_loglik_grad", "mra_predict", "mra_last_failure", "mra_status_string", "mra_destroy"]
+           "mra_loglik_grad", "mra_predict", "mra_last_failure", "mra_profile", "mra_profile_read",
+           "mra_status_string", "mra_destroy"]
 
 
 class Config(C.Structure):
@@ -26,6 +27,11 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_pred", C.c_int64), ("n_rows_pad", C.c_int64), ("n_leaves", C.c_int64),
                 ("n_regions", C.c_int64), ("max_leaf", C.c_int64), ("flops_loglik", C.c_double),
                 ("flops_grad", C.c_double), ("flops_predict", C.c_double)]
+
+
+class PhaseStat(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("level", C.c_int32), ("groups", C.c_int64), ("launches", C.c_int64),
+                ("total_ms", C.c_double), ("flops", C.c_double)]
 
 
 class MRAError(RuntimeError):
@@ -55,6 +61,8 @@ def lib() -> C.CDLL:
     L.mra_loglik_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.mra_predict.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mra_last_failure.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp]
+    L.mra_profile.argtypes = [vp, i32]
+    L.mra_profile_read.argtypes = [vp, C.POINTER(PhaseStat), i32, C.POINTER(i32), vp]
     L.mra_status_string.argtypes = [i32]
     L.mra_status_string.restype = C.c_char_p
     L.mra_destroy.argtypes = [vp]

@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
 #include <new>
+#include <utility>
 
 #include "launch.hpp"
 #include "plan.hpp"
@@ -162,6 +164,7 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  P->last_nth = n_theta;
   s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
@@ -174,6 +177,7 @@ mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_thet
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  P->last_nth = n_theta;
   s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
   if (s != MRA_OK) return s;
   s = check_hip(launch_grad(*P, d_theta, n_theta, d_grad, st));
@@ -189,6 +193,7 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
   if (!d_y || !d_theta || !d_mean || !d_var) return MRA_EINVAL;
   if (P->n_pred == 0) return MRA_OK;
   hipStream_t st = (hipStream_t)stream;
+  P->last_nth = 1;
   s = check_hip(launch_forward(*P, d_y, d_theta, 1, nullptr, st));
   if (s != MRA_OK) return s;
   s = check_hip(launch_predict(*P, d_theta, d_mean, d_var, st));
@@ -200,12 +205,60 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
 mra_status mra_last_failure(mra_plan_t P, int32_t* theta_idx, int32_t* level, int64_t* region, void* stream) {
   if (!P) return MRA_EINVAL;
   if (!(P->cfg.flags & MRA_SYNC) && P->bound) {
-    mra_status s = collect_failures(P, P->cfg.max_theta, (hipStream_t)stream);
+    mra_status s = collect_failures(P, P->last_nth, (hipStream_t)stream);
     if (s == MRA_EHIP) return s;
   }
   if (theta_idx) *theta_idx = P->fail_theta;
   if (level) *level = P->fail_level;
   if (region) *region = P->fail_region;
+  return MRA_OK;
+}
+
+mra_status mra_profile(mra_plan_t P, int32_t enable) {
+  if (!P) return MRA_EINVAL;
+  if (!P->prof) {
+    P->prof = new (std::nothrow) Profiler();
+    if (!P->prof) return MRA_ENOMEM;
+  }
+  P->prof->enabled = enable != 0;
+  P->prof->recs.clear();
+  P->prof->used = 0;
+  return MRA_OK;
+}
+
+mra_status mra_profile_read(mra_plan_t P, mra_phase_stat* out, int32_t cap, int32_t* count, void* stream) {
+  if (!P || !count || (cap > 0 && !out)) return MRA_EINVAL;
+  *count = 0;
+  if (!P->prof) return MRA_OK;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MRA_EHIP;
+  std::map<std::pair<std::string, int>, mra_phase_stat> agg;
+  std::vector<std::pair<std::string, int>> order;
+  for (const ProfRecord& r : P->prof->recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+      return MRA_EHIP;
+    auto key = std::make_pair(std::string(r.name), r.level);
+    auto it = agg.find(key);
+    if (it == agg.end()) {
+      mra_phase_stat s{};
+      std::strncpy(s.name, r.name, sizeof(s.name) - 1);
+      s.level = r.level;
+      it = agg.emplace(key, s).first;
+      order.push_back(key);
+    }
+    it->second.groups += 1;
+    it->second.launches += r.launches;
+    it->second.total_ms += ms;
+    it->second.flops += r.flops;
+  }
+  int32_t k = 0;
+  for (const auto& key : order) {
+    if (k < cap) out[k] = agg[key];
+    ++k;
+  }
+  *count = k;
+  P->prof->recs.clear();
+  P->prof->used = 0;
   return MRA_OK;
 }
 
@@ -221,6 +274,10 @@ const char* mra_status_string(mra_status s) {
   return "unknown status";
 }
 
-void mra_destroy(mra_plan_t P) { delete P; }
+void mra_destroy(mra_plan_t P) {
+  if (!P) return;
+  delete P->prof;
+  delete P;
+}
 
 }  // extern "C"

@@ -338,24 +338,25 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
                           hipStream_t st) {
   const DevPlan& P = H.dp;
+  const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
   int64_t gx = (P.plane + NT - 1) / NT;
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
-  for (int m = 0; m < M; ++m) run(k_prior, P.nreg[m], theta, m);
-  run(k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
-  run(k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
-  run(k_leaf_potrf, (int64_t)H.fac_tasks.size());
-  run(k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
+  for (int m = 0; m < M; ++m) run("prior", m, F.prior[m], k_prior, P.nreg[m], theta, m);
+  run("leaf_rows", -1, F.leaf_rows, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
+  run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
+  run("leaf_potrf", -1, F.potrf, k_leaf_potrf, (int64_t)H.fac_tasks.size());
+  run("leaf_trsm", -1, F.trsm, k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
   if (M == 0) {
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
-    run(k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    run("leaf_reduce", -1, F.leaf_reduce, k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
-      run(k_post, P.nreg[m], m, out_loglik);
-      if (m > 0) run(k_post_reduce, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+      run("post", m, F.post[m], k_post, P.nreg[m], m, out_loglik);
+      if (m > 0) run("post_reduce", m, F.post_reduce[m], k_post_reduce, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);

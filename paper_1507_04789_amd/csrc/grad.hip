@@ -497,23 +497,24 @@ __global__ void k_zero_gpart(DevPlan P, int64_t nslot) {
 
 hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st) {
   const DevPlan& P = H.dp;
+  const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
-  for (int m = 0; m < M; ++m) run(k_rpost, P.nreg[m], m);
-  run(k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
-  run(k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
-  run(k_rleaf_q, nrow * (M + 1));
-  run(k_rleaf_sbar, P.n_sig_tasks, theta);
+  for (int m = 0; m < M; ++m) run("rpost", m, F.rpost[m], k_rpost, P.nreg[m], m);
+  run("rleaf_v", -1, F.rleaf_v, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
+  run("rleaf_linv", -1, F.rleaf_linv, k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
+  run("rleaf_q", -1, F.rleaf_q, k_rleaf_q, nrow * (M + 1));
+  run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
   if (M > 0) {
-    run(k_rleaf_wbar, nrow * M);
-    run(k_rrows_leaf, nrow, theta);
-    run(k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    run("rleaf_wbar", -1, F.rleaf_wbar, k_rleaf_wbar, nrow * M);
+    run("rrows_leaf", -1, F.rrows, k_rrows_leaf, nrow, theta);
+    run("rT_leaf", -1, F.rT_leaf, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
-      run(k_rprior, P.nreg[m], theta, m);
-      if (m > 0) run(k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+      run("rprior", m, F.rprior[m], k_rprior, P.nreg[m], theta, m);
+      if (m > 0) run("rT", m, F.rT[m], k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   hipLaunchKernelGGL(k_gsum, dim3(nth), dim3(NT), 0, st, P, theta, out_grad, nslot);

@@ -1,8 +1,12 @@
 // Launch helper shared by the kernel files: a batch of independent tasks is
 // one launch (grid.x = tasks, grid.y = parameter vectors), or, in the plain
-// comparison form, one launch per task.
+// comparison form, one launch per task.  With profiling enabled every launch
+// group is bracketed by HIP events on the call's stream.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
 
 #include "devplan.hpp"
 
@@ -10,19 +14,56 @@ struct mra_plan_s;
 
 namespace mra {
 
+struct ProfRecord {
+  const char* name;
+  int level;
+  double flops;          // algorithmic flops of the group (all parameter vectors)
+  int64_t launches;
+  hipEvent_t start, stop;
+};
+
+struct Profiler {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRecord> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct Runner {
   const DevPlan& P;
   int nth;
   hipStream_t st;
   bool plain;
+  Profiler* prof;
   template <class K, class... A>
-  void operator()(K kern, int64_t ntask, A... args) const {
+  void operator()(const char* name, int level, double flops, K kern, int64_t ntask, A... args) const {
     if (ntask <= 0) return;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof && prof->enabled) {
+      e0 = prof->next();
+      e1 = prof->next();
+      if (e0) (void)hipEventRecord(e0, st);
+    }
     if (plain) {
       for (int64_t t = 0; t < ntask; ++t)
         hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., t);
     } else {
       hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., (int64_t)0);
+    }
+    if (e0 && e1) {
+      (void)hipEventRecord(e1, st);
+      prof->recs.push_back(ProfRecord{name, level, flops * nth, plain ? ntask : 1, e0, e1});
     }
   }
 };

@@ -296,64 +296,65 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.theta_stride = w;
 
   // ---- algorithmic flop model (actual r, not the padded tile) ----
-  const double rr = r;
-  double fl = 0.0;
+  // Counts multiply-adds as 2 flops; symmetric products count one triangle;
+  // triangular solves and products count r^2 per right-hand side column.
+  PhaseFlops& F = P->pf;
+  F = PhaseFlops{};
+  const double rr = r, Mr = M * rr;
   for (int m = 0; m < M; ++m) {
-    double per = 0.0;
-    for (int l = 0; l < m; ++l) per += 2.0 * rr * rr * (l * rr) + rr * rr * rr;   // GEMM + TRSM
-    per += rr * rr * (m * rr) + rr * rr * rr / 3.0;                                  // SYRK + POTRF
-    fl += per * P->nreg[m];
-  }
-  double fl_post = 0.0;
-  for (int m = 0; m < M; ++m) {
-    double per = rr * rr * rr / 3.0 + rr * rr * (m * rr + 1) + (m * rr + 1) * (m * rr + 1) * rr;
-    fl_post += per * P->nreg[m];
-  }
-  double fl_leaf = 0.0;
-  const double Mr = M * rr;
-  for (int64_t i = 0; i < n_leaves; ++i) {
-    double nr = P->leaf_n[i];
-    if (nr == 0) continue;
-    fl_leaf += nr * rr * rr * (double)(M * (M - 1) + M);     // rows of W^ (GEMM + TRSM)
-    fl_leaf += nr * nr * Mr;                                 // Sigma (SYRK)
-    fl_leaf += nr * nr * nr / 3.0;                           // POTRF
-    fl_leaf += nr * nr * (Mr + 1);                           // TRSM of [W^ | z]
-    fl_leaf += nr * (Mr + 1) * (Mr + 1);                     // [W^ | z]' Sigma^{-1} [W^ | z] (SYRK)
-  }
-  P->flops_loglik = fl + fl_post + fl_leaf;
-  // reverse pass: the posterior reverse needs V, V Fbar and V Fbar V' per
-  // region; the leaf reverse V, Q = V Fbar, Sigma-bar, W^-bar; the prior
-  // reverse mirrors the row sweeps plus the T reductions
-  double rv = 0.0;
-  for (int m = 0; m < M; ++m) {
-    double k = m * rr + 1;
-    rv += P->nreg[m] * (rr * rr * k + 2.0 * rr * k * k + 2.0 * rr * rr * k + 2.0 * rr * rr * rr);
-    double per = 0.0;
-    for (int l = 0; l < m; ++l) per += 2.0 * rr * rr * (l * rr) + 2.0 * rr * rr * rr + 2.0 * rr * rr * ((l + 1) * rr);
-    rv += per * P->nreg[m] + 4.0 * rr * rr * rr * P->nreg[m];
+    const double R = (double)P->nreg[m];
+    double pr = rr * rr * (m * rr) + rr * rr * rr / 3.0;                  // SYRK + POTRF
+    for (int l = 0; l < m; ++l) pr += 2.0 * rr * rr * (l * rr) + rr * rr * rr;   // GEMM + TRSM
+    F.prior[m] = R * pr;
+    const double k = m * rr + 1;
+    F.post[m] = R * (rr * rr * rr / 3.0 + rr * rr * k);                        // POTRF + TRSM of [A^{m,<m} | w^m]
+    // children of level m summed into level m-1: A~ = A - Z'Z per child
+    if (m > 0) F.post_reduce[m] = R * (m * rr) * (m * rr + 1) * rr + R * 2.0 * (m * rr) * rr;
+    // reverse: V = Lt^{-T} Z, Xbar = 2 V Fbar, Pbar = -V Fbar V' - P^{-1}/2
+    F.rpost[m] = R * (rr * rr * k + 2.0 * rr * (m * rr) * (m * rr) + 2.0 * rr * rr * (m * rr) + rr * rr * rr);
+    // Cholesky adjoint (3 triangular products), -2 Wbar^m W^^k, reverse row sweep
+    double rp = 3.0 * rr * rr * rr + 2.0 * rr * rr * (m * rr);
+    for (int l = 0; l < m; ++l) rp += 2.0 * rr * rr * rr + 2.0 * rr * rr * (l * rr);
+    F.rprior[m] = R * rp;
+    // subtree sums of level m (children) into level m-1: Wbar^l' W^^k, k <= l < m
+    double rt = 0.0;
+    for (int l = 0; l < m; ++l) rt += 2.0 * rr * rr * ((l + 1) * rr);
+    F.rT[m] = R * rt;
   }
   for (int64_t i = 0; i < n_leaves; ++i) {
-    double nr = P->leaf_n[i];
+    const double nr = P->leaf_n[i];
     if (nr == 0) continue;
-    rv += nr * nr * (Mr + 1);                 // V = L^{-T} Y
-    rv += 2.0 * nr * (Mr + 1) * (Mr + 1);     // Q = V Fbar
-    rv += 2.0 * nr * nr * (Mr + 1);           // Sigma-bar = -Q V'
-    rv += 2.0 * nr * nr * nr / 3.0;           // Sigma^{-1}
-    rv += 2.0 * nr * nr * Mr;                 // Sigma-bar W^
-    double per = 0.0;                         // per row: W-bar^l, W^-bar updates, T contributions
-    for (int l = 0; l < M; ++l) per += 2.0 * rr * rr + 2.0 * rr * rr * l + 2.0 * rr * rr * (l + 1);
-    rv += nr * per;
+    F.leaf_rows += nr * rr * rr * (double)(M * (M - 1) + M);   // rows of W^: GEMM + TRSM per level
+    F.sigma += nr * nr * Mr;                                   // Sigma_R (SYRK)
+    F.potrf += nr * nr * nr / 3.0;
+    F.trsm += nr * nr * (Mr + 1);                              // L^{-1} [W^ | z]
+    F.leaf_reduce += nr * (Mr + 1) * (Mr + 1);                 // [W^ | z]' Sigma^{-1} [W^ | z]
+    F.rleaf_v += nr * nr * (Mr + 1);                           // L^{-T} Y
+    F.rleaf_linv += nr * nr * nr / 3.0;                        // L^{-1}
+    F.rleaf_q += 2.0 * nr * (Mr + 1) * (Mr + 1);               // V Fbar
+    F.rleaf_sbar += nr * nr * (Mr + 1) + nr * nr * nr / 3.0;   // -Q V' - Sigma^{-1}/2 (lower half)
+    F.rleaf_wbar += 2.0 * nr * nr * Mr;                        // Sigma-bar W^
+    F.rrows += nr * rr * rr * (double)(2 * M + M * (M - 1));   // Wbar^l = W^bar L^{-1}, W^-bar updates
+    F.rT_leaf += nr * rr * rr * (double)(M * (M + 1));         // Wbar^l' W^^k, k <= l
   }
-  P->flops_grad = P->flops_loglik + rv;
+  double fl = F.leaf_rows + F.sigma + F.potrf + F.trsm + F.leaf_reduce;
+  double rv = F.rleaf_v + F.rleaf_linv + F.rleaf_q + F.rleaf_sbar + F.rleaf_wbar + F.rrows + F.rT_leaf;
+  for (int m = 0; m < M; ++m) {
+    fl += F.prior[m] + F.post[m] + F.post_reduce[m];
+    rv += F.rpost[m] + F.rprior[m] + F.rT[m];
+  }
+  P->flops_loglik = fl;
+  P->flops_grad = fl + rv;
   double fp = 0.0;
   for (int64_t i = 0; i < n_leaves; ++i) {
-    double np = P->pleaf_n[i], nr = P->leaf_n[i];
+    const double np = P->pleaf_n[i], nr = P->leaf_n[i];
     if (np == 0) continue;
     fp += np * rr * rr * (double)(M * (M - 1) + M);     // U^ rows
-    fp += 2.0 * np * nr * Mr + np * nr * nr;             // L^M and L^M L^{-T}
+    fp += 2.0 * np * nr * Mr + np * nr * nr;             // L^M and E = L^M L^{-T}
     fp += 2.0 * np * nr * Mr;                            // B~^M
     for (int l = 0; l < M; ++l) fp += np * (rr * rr + 2.0 * rr * rr * l);
   }
+  F.predict = fp;
   P->flops_predict = fp;
   return MRA_OK;
 }

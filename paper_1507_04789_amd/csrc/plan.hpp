@@ -12,6 +12,17 @@
 namespace mra {
 
 struct GraphCache;  // defined in api.cpp
+struct Profiler;    // defined in launch.hpp
+
+// Algorithmic FP64 flops of each launch group for one parameter vector
+// (actual r and leaf counts; padding and recomputation are not counted).
+struct PhaseFlops {
+  double prior[MAXL], post[MAXL], post_reduce[MAXL];
+  double leaf_rows, sigma, potrf, trsm, leaf_reduce;
+  double rpost[MAXL], rprior[MAXL], rT[MAXL];
+  double rleaf_v, rleaf_linv, rleaf_q, rleaf_sbar, rleaf_wbar, rrows, rT_leaf;
+  double predict;
+};
 
 struct Layout {
   // geometry arena (byte offsets)
@@ -57,6 +68,9 @@ struct mra_plan_s {
   int32_t fail_theta = -1, fail_level = -1;
   int64_t fail_region = -1;
   mra::GraphCache* graphs = nullptr;
+  mra::PhaseFlops pf;
+  mra::Profiler* prof = nullptr;
+  int32_t last_nth = 1;
 };
 
 namespace mra {
