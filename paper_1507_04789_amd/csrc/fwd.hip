@@ -54,9 +54,8 @@ __global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, in
   for (int k = 0; k < m; ++k) gemm<Op::N, Op::T>(acc, reg + k * TT, T, reg + k * TT, T, T, -1.0, lds);
   acc_to_lds(acc, lds);
   __syncthreads();
-  if (!potrf_lds(lds) && threadIdx.x == 0) record_failure(P, S, m, i);
+  if (!potrf_trtri(lds, reg + (m + 1) * TT) && threadIdx.x == 0) record_failure(P, S, m, i);
   lds_to_global(lds, reg + m * TT);
-  trtri_lds_to_global(lds, reg + (m + 1) * TT);
 }
 
 // rows of W^ for the observations of one 64-row leaf tile
@@ -113,10 +112,10 @@ __global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, int64_t t0) {
     double* Dk = base + ((int64_t)kb * nb + kb) * TT;
     tile_to_lds(Dk, T, lds);
     __syncthreads();
-    ok = potrf_lds(lds) && ok;
+    ok = potrf_trtri(lds, dinv + (int64_t)kb * TT) && ok;
     logdet += 2.0 * logdiag_lds(lds, min(T, nR - kb * T), red);
     lds_to_global(lds, Dk);
-    trtri_lds_to_global(lds, dinv + (int64_t)kb * TT);
+    __syncthreads();
     for (int ib = kb + 1; ib < nb; ++ib) {
       double* X = base + ((int64_t)ib * nb + kb) * TT;
       acc_zero(acc);
@@ -195,13 +194,16 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, int64_t t0) {
     for (int64_t p = p0; p < p1; p += T) gemm<Op::T, Op::N>(acc, Yk + p * T, T, Yl + p * T, T, T, 1.0, lds);
   }
   acc_store(acc, po.A(k, l), T);
-  if (k == l && threadIdx.x < T) {
+  if (k == l) {      // w^k = sum_c Y^k_c' y_c: column threadIdx & 63, rows split over the waves
     double w = 0.0;
+    const int col = threadIdx.x & 63;
     for (int c = 0; c < P.J; ++c) {
       const int64_t leaf = pidx * P.J + c;
-      for (int64_t p = P.leaf_poff[leaf]; p < P.leaf_poff[leaf + 1]; ++p) w += Yk[p * T + threadIdx.x] * Yz[p * T];
+      for (int64_t p = P.leaf_poff[leaf] + wave_id(); p < P.leaf_poff[leaf + 1]; p += 4)
+        w += Yk[p * T + col] * Yz[p * T];
     }
-    po.omega(k)[threadIdx.x] = w;
+    w = wave_col_sum(w, lds);
+    if (threadIdx.x < T) po.omega(k)[threadIdx.x] = w;
   }
   if (kl == 0) {
     double u = 0.0;
@@ -232,10 +234,10 @@ __global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_logli
   __syncthreads();
   if (threadIdx.x < T) lds[threadIdx.x * PLD + threadIdx.x] += 1.0;
   __syncthreads();
-  const bool ok = potrf_lds(lds);
+  const bool ok = potrf_trtri(lds, po.Lti());
   const double ld = 2.0 * logdiag_lds(lds, T, red);
   lds_to_global(lds, po.Lt());
-  trtri_lds_to_global(lds, po.Lti());
+  __syncthreads();
   Acc acc;
   for (int l = 0; l < m; ++l) {
     acc_zero(acc);
@@ -285,17 +287,18 @@ __global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, int64_t t0
     gemm<Op::T, Op::N>(acc, pc.Z(k), T, pc.Z(l), T, T, -1.0, lds);
   }
   acc_store(acc, pp.A(k, l), T);
-  if (k == l && threadIdx.x < T) {
+  if (k == l) {      // w^k_P = sum_c (w^k_c - Z^k_c' z_c)
     double w = 0.0;
+    const int col = threadIdx.x & 63;
     for (int c = 0; c < P.J; ++c) {
       Post pc = post_of(P, S, m, pidx * P.J + c);
-      double s = pc.omega(k)[threadIdx.x];
       const double* Zk = pc.Z(k);
       const double* zw = pc.zw();
-      for (int q = 0; q < T; ++q) s -= Zk[q * T + threadIdx.x] * zw[q];
-      w += s;
+      if (wave_id() == 0) w += pc.omega(k)[col];
+      for (int q = wave_id(); q < T; q += 4) w -= Zk[q * T + col] * zw[q];
     }
-    pp.omega(k)[threadIdx.x] = w;
+    w = wave_col_sum(w, lds);
+    if (threadIdx.x < T) pp.omega(k)[threadIdx.x] = w;
   }
   if (kl == 0 && threadIdx.x == 0) {
     double dsum = 0.0, usum = 0.0;

@@ -113,14 +113,17 @@ __global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
         for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] -= vw[acc_row(bi, v)] * wb[acc_col(bj)];
     acc_store(acc, gr.G(l), T);
   }
-  if (threadIdx.x < T) {              // xbar_w = -sum_k V_k wbar^k + v_w
-    double s = vw[threadIdx.x];
+  {                                   // xbar_w = -sum_k V_k wbar^k + v_w, four threads per row
+    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;
+    double s = 0.0;
     for (int k = 0; k < m; ++k) {
-      const double* Vk = V0 + (int64_t)k * TT + threadIdx.x * T;
-      const double* wb = wbar_omega_of(P, S, k, m, i);
-      for (int j = 0; j < T; ++j) s -= Vk[j] * wb[j];
+      const double* Vk = V0 + (int64_t)k * TT + r * T + part * 16;
+      const double* wb = wbar_omega_of(P, S, k, m, i) + part * 16;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s += Vk[j] * wb[j];
     }
-    gr.wbar_omega()[threadIdx.x] = s;
+    s = quad_sum(s);
+    if (part == 0) gr.wbar_omega()[r] = vw[r] - s;
   }
   __syncthreads();
   // Pbar = -1/2 (sum_l Xbar_l V_l' + xbar_w v_w' + Lt^{-T} Lt^{-1})
@@ -225,22 +228,21 @@ __global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, int64_t t0) {
         for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] += 0.5 * vz[acc_row(bi, v) * T] * wb[acc_col(bj)];
     acc_store(acc, Q, T);
   } else {
-    // q_z = 1/2 sum_k V_k wbar^k - 1/2 v_z in column 0, zero elsewhere
-    for (int e = threadIdx.x; e < TT; e += NT) {
-      int r = e >> 6, col = e & 63;
-      double s = 0.0;
-      if (col == 0) {
-        s = -0.5 * vz[r * T];
-        for (int k = 0; k < M; ++k) {
-          const double* Vk = V + (int64_t)k * P.plane + r * T;
-          const double* wb = wbar_omega_of(P, S, k, M, leaf);
-          double t = 0.0;
-          for (int j = 0; j < T; ++j) t += Vk[j] * wb[j];
-          s += 0.5 * t;
-        }
-      }
-      Q[e] = s;
+    // q_z = 1/2 sum_k V_k wbar^k - 1/2 v_z in column 0, zero elsewhere;
+    // four threads per row, each over a quarter of the columns
+    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;
+    double s = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double* Vk = V + (int64_t)k * P.plane + r * T + part * 16;
+      const double* wb = wbar_omega_of(P, S, k, M, leaf) + part * 16;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s += Vk[j] * wb[j];
     }
+    s = quad_sum(s);
+    double* qr = Q + r * T + part * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) qr[j] = 0.0;
+    if (part == 0) qr[0] = 0.5 * s - 0.5 * vz[r * T];
   }
 }
 

@@ -24,7 +24,8 @@ constexpr int NT = 256;       // threads per workgroup
 constexpr int KC = 16;        // k-chunk staged in LDS
 constexpr int SLD = T + 4;    // LDS row pitch of a staged chunk (doubles)
 constexpr int PLD = T + 1;    // LDS row pitch of a factorisation tile
-constexpr int LDS_DOUBLES = T * PLD;   // >= 2 * KC * SLD
+constexpr int LDS_DOUBLES = 4 * KC * SLD;   // two stages of A and B chunks
+static_assert(LDS_DOUBLES >= T * PLD, "the LDS buffer also holds one factorisation tile");
 
 struct Acc {
   d4 c[2][2];
@@ -66,48 +67,56 @@ __device__ __forceinline__ void acc_store(const Acc& a, double* C, int ldc) {
       for (int v = 0; v < 4; ++v) C[(int64_t)acc_row(bi, v) * ldc + acc_col(bj)] = a.c[bi][bj][v];
 }
 
-// ---------------------------------------------------------------------------
-// chunk loaders: fill s[k][i] (pitch SLD) for k in [0, KC), i in [0, T)
-// ---------------------------------------------------------------------------
-
-// element (i, k) = p[i * ld + k0 + k]  (row-major rows, k contiguous)
-__device__ __forceinline__ void load_rows(double* s, const double* p, int ld, int k0) {
-  const int t = threadIdx.x;
-  const int i = t >> 2, kq = (t & 3) * 4;
-  d4 v = *(const d4*)(p + (int64_t)i * ld + k0 + kq);
-  s[(kq + 0) * SLD + i] = v[0];
-  s[(kq + 1) * SLD + i] = v[1];
-  s[(kq + 2) * SLD + i] = v[2];
-  s[(kq + 3) * SLD + i] = v[3];
-}
-
-// element (i, k) = p[(k0 + k) * ld + i]  (k-major, i contiguous)
-__device__ __forceinline__ void load_cols(double* s, const double* p, int ld, int k0) {
-  const int t = threadIdx.x;
-  const int k = t >> 4, iq = (t & 15) * 4;
-  d4 v = *(const d4*)(p + (int64_t)(k0 + k) * ld + iq);
-  *(d4*)(s + k * SLD + iq) = v;
-}
-
 enum class Op { N, T };
 
 // acc += alpha * opA(A) * opB(B) over K (multiple of KC), 64x64 output.
 //   opA = N: A(i,k) = A[i*lda + k]  ;  opA = T: A(i,k) = A[k*lda + i]
 //   opB = T: B(k,j) = B[j*ldb + k]  ;  opB = N: B(k,j) = B[k*ldb + j]
-// Ends with a barrier, so the caller may overwrite A or B afterwards.
+// Two LDS stages: the global loads of chunk c+1 are in flight while the
+// MFMAs of chunk c run; one barrier per chunk.  Ends with a barrier, so the
+// caller may overwrite A or B afterwards.
+template <Op OA>
+__device__ __forceinline__ d4 fetch(const double* p, int ld, int k0) {
+  const int t = threadIdx.x;
+  if (OA == Op::N) return *(const d4*)(p + (int64_t)(t >> 2) * ld + k0 + (t & 3) * 4);
+  return *(const d4*)(p + (int64_t)(k0 + (t >> 4)) * ld + (t & 15) * 4);
+}
+template <Op OA>
+__device__ __forceinline__ void stash(double* s, d4 v) {
+  const int t = threadIdx.x;
+  if (OA == Op::N) {
+    const int i = t >> 2, kq = (t & 3) * 4;
+    s[(kq + 0) * SLD + i] = v[0];
+    s[(kq + 1) * SLD + i] = v[1];
+    s[(kq + 2) * SLD + i] = v[2];
+    s[(kq + 3) * SLD + i] = v[3];
+  } else {
+    *(d4*)(s + (t >> 4) * SLD + (t & 15) * 4) = v;
+  }
+}
+
 template <Op OA, Op OB>
 __device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const double* B, int ldb, int K,
                                      double alpha, double* lds) {
-  double* sA = lds;
-  double* sB = lds + KC * SLD;
+  constexpr Op LB = (OB == Op::T) ? Op::N : Op::T;   // B(k,j) = B^T(j,k): same loader roles
   const int w = wave_id(), l = lane_id();
   const int ia = 32 * (w >> 1) + (l & 15);
   const int jb = 32 * (w & 1) + (l & 15);
   const int kr = l >> 4;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    if (OA == Op::N) load_rows(sA, A, lda, k0); else load_cols(sA, A, lda, k0);
-    if (OB == Op::T) load_rows(sB, B, ldb, k0); else load_cols(sB, B, ldb, k0);
-    __syncthreads();
+  const int nch = K / KC;
+  d4 va = fetch<OA>(A, lda, 0);
+  d4 vb = fetch<LB>(B, ldb, 0);
+  stash<OA>(lds, va);
+  stash<LB>(lds + KC * SLD, vb);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    double* sA = lds + (c & 1) * 2 * KC * SLD;
+    double* sB = sA + KC * SLD;
+    const bool more = c + 1 < nch;
+    if (more) {
+      va = fetch<OA>(A, lda, (c + 1) * KC);
+      vb = fetch<LB>(B, ldb, (c + 1) * KC);
+    }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const double* ra = sA + (kk + kr) * SLD;
@@ -118,6 +127,11 @@ __device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const d
       acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
       acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
       acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+    }
+    if (more) {
+      double* nA = lds + ((c + 1) & 1) * 2 * KC * SLD;
+      stash<OA>(nA, va);
+      stash<LB>(nA + KC * SLD, vb);
     }
     __syncthreads();
   }
@@ -143,36 +157,195 @@ __device__ __forceinline__ void tile_to_lds(const double* C, int ldc, double* s)
   }
 }
 
-// In-place lower Cholesky of the symmetric tile in s (lower triangle read).
-// Returns (uniformly) false if a pivot is not positive; the factor then
-// carries NaN.  Upper triangle is zeroed.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// In-place lower Cholesky of the symmetric tile in s (lower triangle read),
+// left-looking, by wave 0: lane i owns row i of s; column j is
+// a_ij - sum_{k<j} L_ik L_jk (row j read as an LDS broadcast), the pivot
+// comes from lane j by readlane.  A wave's LDS accesses complete in order,
+// so column j is visible to every lane in the next step.  Returns
+// (uniformly) false if a pivot is not positive; the factor then carries NaN.
+// The upper triangle is zeroed.
 __device__ inline bool potrf_lds(double* s) {
   __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < T; ++j) {
-    if (threadIdx.x == 0) {
-      double p = s[j * PLD + j];
-      if (!(p > 0.0)) { bad = 1; p = __builtin_nan(""); }
-      s[j * PLD + j] = sqrt(p);
+  if (threadIdx.x < T) {
+    const int i = threadIdx.x;
+    double* ri = s + i * PLD;
+    int ok = 1;
+    for (int j = 0; j < T; ++j) {
+      const double* rj = s + j * PLD;
+      double a0 = ri[j], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = 0;
+      for (; k + 3 < j; k += 4) {
+        a0 = fma(-ri[k], rj[k], a0);
+        a1 = fma(-ri[k + 1], rj[k + 1], a1);
+        a2 = fma(-ri[k + 2], rj[k + 2], a2);
+        a3 = fma(-ri[k + 3], rj[k + 3], a3);
+      }
+      for (; k < j; ++k) a0 = fma(-ri[k], rj[k], a0);
+      const double a = (a0 + a1) + (a2 + a3);
+      const double p = readlane_d(a, j);
+      ok &= (p > 0.0) ? 1 : 0;
+      const double d = (p > 0.0) ? sqrt(p) : __builtin_nan("");
+      const double inv = 1.0 / d;
+      ri[j] = (i > j) ? a * inv : (i == j ? d : 0.0);
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    const double inv = 1.0 / s[j * PLD + j];
-    for (int i = j + 1 + threadIdx.x; i < T; i += NT) s[i * PLD + j] *= inv;
-    __syncthreads();
-    const int m = T - 1 - j;
-    for (int e = threadIdx.x; e < m * m; e += NT) {
-      int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) s[i * PLD + k] -= s[i * PLD + j] * s[k * PLD + j];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    int i = e >> 6, k = e & 63;
-    if (k > i) s[i * PLD + k] = 0.0;
+    if (i == 0) bad = !ok;
   }
   __syncthreads();
   return bad == 0;
+}
+
+// ---------------------------------------------------------------------------
+// 16x16 block helpers for one wave (MFMA 16x16x4 layout as above)
+// ---------------------------------------------------------------------------
+
+// acc += alpha * A B^T, A and B 16 x K row-major (pitches lda, ldb)
+__device__ __forceinline__ void mfma_abt(d4& acc, const double* A, int lda, const double* B, int ldb, int K,
+                                         double alpha) {
+  const int l = lane_id();
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double a = alpha * A[(l & 15) * lda + k0 + (l >> 4)];
+    const double b = B[(l & 15) * ldb + k0 + (l >> 4)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+}
+// acc += alpha * A B, A 16 x K, B K x 16, row-major
+__device__ __forceinline__ void mfma_ab(d4& acc, const double* A, int lda, const double* B, int ldb, int K,
+                                        double alpha) {
+  const int l = lane_id();
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double a = alpha * A[(l & 15) * lda + k0 + (l >> 4)];
+    const double b = B[(k0 + (l >> 4)) * ldb + (l & 15)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+}
+__device__ __forceinline__ void blk_store(const d4& acc, double* C, int ldc) {
+  const int l = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(4 * v + (l >> 4)) * ldc + (l & 15)] = acc[v];
+}
+__device__ __forceinline__ void blk_load(d4& acc, const double* C, int ldc) {
+  const int l = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = C[(4 * v + (l >> 4)) * ldc + (l & 15)];
+}
+
+// Lower Cholesky of the 16x16 block D (pitch PLD) in place, left-looking, by
+// lanes 0..15 of one wave (lane i owns row i); upper part zeroed.  Returns
+// 1 if every pivot was positive (uniform over the wave).
+__device__ __forceinline__ int potrf16(double* D) {
+  const int i = lane_id();
+  int ok = 1;
+  for (int j = 0; j < 16; ++j) {
+    double a = 0.0;
+    if (i < 16) {
+      const double* ri = D + i * PLD;
+      const double* rj = D + j * PLD;
+      a = ri[j];
+      for (int k = 0; k < j; ++k) a = fma(-ri[k], rj[k], a);
+    }
+    const double p = readlane_d(a, j);
+    ok &= (p > 0.0) ? 1 : 0;
+    const double d = (p > 0.0) ? sqrt(p) : __builtin_nan("");
+    const double inv = 1.0 / d;
+    if (i < 16) D[i * PLD + j] = (i > j) ? a * inv : (i == j ? d : 0.0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return ok;
+}
+
+// X (pitch ldx) = inverse of the lower-triangular 16x16 block D (pitch PLD),
+// by lanes 0..15 of one wave (lane j computes column j)
+__device__ __forceinline__ void trtri16(const double* D, double* X, int ldx) {
+  const int j = lane_id();
+  if (j < 16) {
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double acc = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < r; ++k) acc = fma(-D[r * PLD + k], x[k], acc);
+      x[r] = acc / D[r * PLD + r];
+      __builtin_amdgcn_sched_barrier(0);   // keep each row's loads next to their use
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[r * ldx + j] = x[r];
+  }
+}
+
+// Blocked lower Cholesky of the symmetric 64x64 tile in s (lower triangle
+// read; 4x4 blocks of 16) and the inverse of the factor, Linv (global, ld T).
+// Diagonal blocks are factored and inverted by wave 0; panel and trailing
+// updates and the off-diagonal blocks of the inverse
+//   X_ii = L_ii^{-1},  X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj  (i > j)
+// run on MFMA across the four waves.  On return s holds L (upper part zero).
+// Returns false (uniformly) if a pivot was not positive; the factor and the
+// inverse then carry NaN.
+__device__ inline bool potrf_trtri(double* s, double* Linv) {
+  __shared__ int ok_all;
+  const int w = wave_id();
+  if (threadIdx.x == 0) ok_all = 1;
+  __syncthreads();
+  for (int kb = 0; kb < 4; ++kb) {
+    double* Dk = s + 16 * kb * PLD + 16 * kb;
+    double* Xk = Linv + 16 * kb * T + 16 * kb;
+    if (w == 0) {
+      const int ok = potrf16(Dk);
+      if (lane_id() == 0 && !ok) ok_all = 0;
+      trtri16(Dk, Xk, T);
+    }
+    __syncthreads();
+    const int ib = kb + 1 + w;                 // panel: L_ik = A_ik X_kk^T
+    if (ib < 4) {
+      double* Aik = s + 16 * ib * PLD + 16 * kb;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      mfma_abt(acc, Aik, PLD, Xk, T, 16, 1.0);
+      blk_store(acc, Aik, PLD);
+    }
+    __syncthreads();
+    int idx = 0;                               // trailing: A_ij -= L_ik L_jk^T, kb < j <= i
+    for (int i2 = kb + 1; i2 < 4; ++i2)
+      for (int j2 = kb + 1; j2 <= i2; ++j2, ++idx)
+        if ((idx & 3) == w) {
+          double* Aij = s + 16 * i2 * PLD + 16 * j2;
+          d4 acc;
+          blk_load(acc, Aij, PLD);
+          mfma_abt(acc, s + 16 * i2 * PLD + 16 * kb, PLD, s + 16 * j2 * PLD + 16 * kb, PLD, 16, -1.0);
+          blk_store(acc, Aij, PLD);
+        }
+    __syncthreads();
+  }
+  // zero the strictly upper blocks of L and of its inverse
+  for (int e = threadIdx.x; e < TT; e += NT) {
+    const int i = e >> 6, j = e & 63;
+    if ((j >> 4) > (i >> 4)) {
+      s[i * PLD + j] = 0.0;
+      Linv[e] = 0.0;
+    }
+  }
+  for (int ib = 1; ib < 4; ++ib) {
+    const int jb = w;
+    double* Xij = Linv + 16 * ib * T + 16 * jb;
+    if (jb < ib) {                             // t = sum_{k=j}^{i-1} L_ik X_kj
+      d4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int kb = jb; kb < ib; ++kb) mfma_ab(t, s + 16 * ib * PLD + 16 * kb, PLD, Linv + 16 * kb * T + 16 * jb, T, 16, 1.0);
+      blk_store(t, Xij, T);
+    }
+    __syncthreads();
+    if (jb < ib) {                             // X_ij = -X_ii t
+      d4 x = {0.0, 0.0, 0.0, 0.0};
+      mfma_ab(x, Linv + 16 * ib * T + 16 * ib, T, Xij, T, 16, -1.0);
+      blk_store(x, Xij, T);
+    }
+    __syncthreads();
+  }
+  return ok_all != 0;
 }
 
 // sum of log of the diagonal of the tile in s over rows [0, nv)
@@ -190,20 +363,37 @@ __device__ inline double logdiag_lds(const double* s, int nv, double* red) {
   return r;
 }
 
-// Linv (global, ld T) = inverse of the lower-triangular tile in s.
-// Column j of the inverse solves L x = e_j by forward substitution.
-__device__ inline void trtri_lds_to_global(const double* s, double* Linv) {
-  const int j = threadIdx.x;
-  if (j < T) {
-    for (int i = 0; i < j; ++i) Linv[i * T + j] = 0.0;
-    double xj = 1.0 / s[j * PLD + j];
-    Linv[j * T + j] = xj;
-    // x kept in registers would need 64 of them; stream through global/L1
-    for (int i = j + 1; i < T; ++i) {
-      double acc = 0.0;
-      for (int k = j; k < i; ++k) acc += s[i * PLD + k] * Linv[k * T + j];
-      Linv[i * T + j] = -acc / s[i * PLD + i];
+// Linv (global, ld T) = inverse of the lower-triangular tile in s, by wave 0:
+// lane j solves L x = e_j by forward substitution; every lane reads the
+// same L entries (LDS broadcast) and keeps its column x in the free upper
+// triangle of its own row of s (x_i at s[j][i], i > j; 1/L_jj apart).
+// Overwrites the upper triangle of s.
+__device__ inline void trtri_lds_to_global(double* s, double* Linv) {
+  __shared__ double dg[T];
+  if (threadIdx.x < T) dg[threadIdx.x] = 1.0 / s[threadIdx.x * PLD + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < T) {
+    const int j = threadIdx.x;
+    double* xr = s + j * PLD;
+    const double xj = dg[j];
+    for (int i = 1; i < T; ++i) {
+      const double* Li = s + i * PLD;
+      double a0 = 0.0, a1 = 0.0;
+      int k = 0;
+      for (; k + 1 < i; k += 2) {
+        const double x0 = (k > j) ? xr[k] : (k == j ? xj : 0.0);
+        const double x1 = (k + 1 > j) ? xr[k + 1] : (k + 1 == j ? xj : 0.0);
+        a0 = fma(Li[k], x0, a0);
+        a1 = fma(Li[k + 1], x1, a1);
+      }
+      if (k < i) a0 = fma(Li[k], (k > j) ? xr[k] : (k == j ? xj : 0.0), a0);
+      if (i > j) xr[i] = -(a0 + a1) * dg[i];
     }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TT; e += NT) {
+    const int i = e >> 6, jj = e & 63;
+    Linv[e] = (i > jj) ? s[jj * PLD + i] : (i == jj ? dg[i] : 0.0);
   }
   __syncthreads();
 }
@@ -213,6 +403,25 @@ __device__ __forceinline__ void lds_to_global(const double* s, double* C) {
     int i = e >> 6, j = e & 63;
     C[i * T + j] = s[i * PLD + j];
   }
+}
+
+// sum over the 4 lanes t, t^1, t^2, t^3 (valid in each of them)
+__device__ __forceinline__ double quad_sum(double x) {
+  x += __shfl_xor(x, 1);
+  x += __shfl_xor(x, 2);
+  return x;
+}
+
+// column sums over the four waves: thread t holds a partial for column
+// t & 63; returns the total in threads 0..63 (others get 0)
+__device__ inline double wave_col_sum(double x, double* red4x64) {
+  red4x64[threadIdx.x] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < T) s = red4x64[threadIdx.x] + red4x64[T + threadIdx.x] + red4x64[2 * T + threadIdx.x] +
+                           red4x64[3 * T + threadIdx.x];
+  __syncthreads();
+  return s;
 }
 
 // block-wide sum (result valid in every thread)
