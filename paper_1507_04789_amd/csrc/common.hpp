@@ -18,6 +18,7 @@ __device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, 
   return i;
 }
 __device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
+__device__ __forceinline__ int round16(int x) { return x <= 0 ? 0 : ((x + 15) & ~15); }
 __device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
   k = 0;
   while ((k + 1) * (k + 2) / 2 <= kl) ++k;
@@ -53,17 +54,19 @@ __device__ __forceinline__ void record_failure(const DevPlan& P, double* S, int 
 __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
                           int64_t bstride, int lev, int64_t idx, double* lds) {
   Acc acc;
+  const int mrows = round16(nx);
   for (int l = 0; l < lev; ++l) {
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
     acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
-    for (int k = 0; k < l; ++k) gemm<Op::N, Op::T>(acc, rows + k * bstride, T, Pa + k * TT, T, T, -1.0, lds);
+    gemm_segs(acc, l, [&](int k) { return seg<Op::N, Op::T>(rows + k * bstride, T, Pa + k * TT, T, -1.0); }, lds,
+              mrows);
     double* out = rows + l * bstride;
     acc_store(acc, out, T);
     __syncthreads();
     acc_zero(acc);
-    gemm<Op::N, Op::T>(acc, out, T, Pa + (l + 1) * TT, T, T, 1.0, lds);   // W^l L_{a_l}^{-T}
-    acc_store(acc, out, T);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::T>(out, T, Pa + (l + 1) * TT, T, 1.0); }, lds, mrows);
+    acc_store(acc, out, T);   // W^l L_{a_l}^{-T}
     __syncthreads();
   }
 }

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, in
   row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds);
   Acc acc;
   acc_cov(acc, X, P.r, X, P.r, c, true, 0.0);
-  for (int k = 0; k < m; ++k) gemm<Op::N, Op::T>(acc, reg + k * TT, T, reg + k * TT, T, T, -1.0, lds);
+  gemm_segs(acc, m, [&](int k) { return seg<Op::N, Op::T>(reg + k * TT, T, reg + k * TT, T, -1.0); }, lds,
+            round16(P.r));
   acc_to_lds(acc, lds);
   __syncthreads();
   if (!potrf_trtri(lds, reg + (m + 1) * TT) && threadIdx.x == 0) record_failure(P, S, m, i);
@@ -87,8 +88,9 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, in
   Acc acc;
   acc_cov(acc, P.obs_xy + 2 * pi, nvi, P.obs_xy + 2 * pj, nvj, c, bi == bj, c.tau2);
   const double* W = S + P.off_wobs;
-  for (int k = 0; k < P.M; ++k)
-    gemm<Op::N, Op::T>(acc, W + k * P.plane + pi * T, T, W + k * P.plane + pj * T, T, T, -1.0, lds);
+  gemm_segs(acc, P.M,
+            [&](int k) { return seg<Op::N, Op::T>(W + k * P.plane + pi * T, T, W + k * P.plane + pj * T, T, -1.0); },
+            lds, round16(nvi));
   acc_store(acc, S + P.off_sig + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT, T);
 }
 
@@ -153,15 +155,19 @@ __global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, int64_t t0) {
   const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
   const double* X = S + P.off_wobs + cpl * P.plane + poff * T;
   double* Y = S + P.off_y + cpl * P.plane + poff * T;
+  const int nR = P.leaf_n[leaf];
   Acc acc;
   for (int ib = 0; ib < nb; ++ib) {
+    const int mr = round16(min(T, nR - T * ib));
     acc_load(acc, X + (int64_t)ib * TT, T);
-    for (int jb = 0; jb < ib; ++jb)
-      gemm<Op::N, Op::N>(acc, base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, T, -1.0, lds);
+    gemm_segs(acc, ib,
+              [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
+              lds, mr);
     acc_store(acc, Y + (int64_t)ib * TT, T);
     __syncthreads();
     acc_zero(acc);
-    gemm<Op::N, Op::N>(acc, dinv + (int64_t)ib * TT, T, Y + (int64_t)ib * TT, T, T, 1.0, lds);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, Y + (int64_t)ib * TT, T, 1.0); },
+              lds, mr);
     acc_store(acc, Y + (int64_t)ib * TT, T);
     __syncthreads();
   }
@@ -188,11 +194,24 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, int64_t t0) {
   const double* Yz = S + P.off_y + (int64_t)M * P.plane;
   Acc acc;
   acc_zero(acc);
+  // segments: the row blocks of the J children, K = valid rows rounded to 16
+  int nsg = 0;
   for (int c = 0; c < P.J; ++c) {
     const int64_t leaf = pidx * P.J + c;
-    const int64_t p0 = P.leaf_poff[leaf], p1 = P.leaf_poff[leaf + 1];
-    for (int64_t p = p0; p < p1; p += T) gemm<Op::T, Op::N>(acc, Yk + p * T, T, Yl + p * T, T, T, 1.0, lds);
+    nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
+  gemm_segs(acc, nsg, [&](int sg) {
+    int64_t leaf = pidx * P.J;
+    int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
+    while (sg >= nbl) {
+      sg -= nbl;
+      ++leaf;
+      nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
+    }
+    const int64_t p = P.leaf_poff[leaf] + (int64_t)sg * T;
+    const int rows = min(T, P.leaf_n[leaf] - T * sg);
+    return seg<Op::T, Op::N>(Yk + p * T, T, Yl + p * T, T, 1.0, round16(rows) / KC);
+  }, lds);
   acc_store(acc, po.A(k, l), T);
   if (k == l) {      // w^k = sum_c Y^k_c' y_c: column threadIdx & 63, rows split over the waves
     double w = 0.0;
@@ -281,11 +300,11 @@ __global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, int64_t t0
   Post pp = post_of(P, S, m - 1, pidx);
   Acc acc;
   acc_zero(acc);
-  for (int c = 0; c < P.J; ++c) {
+  for (int c = 0; c < P.J; ++c) acc_load(acc, post_of(P, S, m, pidx * P.J + c).A(k, l), T, true);
+  gemm_segs(acc, P.J, [&](int c) {
     Post pc = post_of(P, S, m, pidx * P.J + c);
-    acc_load(acc, pc.A(k, l), T, true);
-    gemm<Op::T, Op::N>(acc, pc.Z(k), T, pc.Z(l), T, T, -1.0, lds);
-  }
+    return seg<Op::T, Op::N>(pc.Z(k), T, pc.Z(l), T, -1.0);
+  }, lds);
   acc_store(acc, pp.A(k, l), T);
   if (k == l) {      // w^k_P = sum_c (w^k_c - Z^k_c' z_c)
     double w = 0.0;

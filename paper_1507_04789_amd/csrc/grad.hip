@@ -30,20 +30,13 @@
 
 namespace mra {
 
-// acc += alpha * V * S^{k,c} with S from the cotangents stored at the
+// segment alpha * V * S^{k,c}, S from the cotangents stored at the
 // ancestors a_k, a_c of a region at level `lev`, index `idx`
-__device__ void gemm_S(Acc& acc, const DevPlan& P, double* S, const double* V, int k, int c, int lev, int64_t idx,
-                       double alpha, double* lds) {
-  if (k > c) {
-    Grad g = grad_of(P, S, k, ancestor(P, lev, idx, k));
-    gemm<Op::N, Op::N>(acc, V, T, g.G(c), T, T, 0.5 * alpha, lds);
-  } else if (k < c) {
-    Grad g = grad_of(P, S, c, ancestor(P, lev, idx, c));
-    gemm<Op::N, Op::T>(acc, V, T, g.G(k), T, T, 0.5 * alpha, lds);
-  } else {
-    Grad g = grad_of(P, S, k, ancestor(P, lev, idx, k));
-    gemm<Op::N, Op::N>(acc, V, T, g.G(k), T, T, alpha, lds);
-  }
+__device__ __forceinline__ Seg seg_S(const DevPlan& P, double* S, const double* V, int k, int c, int lev,
+                                     int64_t idx, double alpha) {
+  if (k > c) return seg<Op::N, Op::N>(V, T, grad_of(P, S, k, ancestor(P, lev, idx, k)).G(c), T, 0.5 * alpha);
+  if (k < c) return seg<Op::N, Op::T>(V, T, grad_of(P, S, c, ancestor(P, lev, idx, c)).G(k), T, 0.5 * alpha);
+  return seg<Op::N, Op::N>(V, T, grad_of(P, S, k, ancestor(P, lev, idx, k)).G(k), T, alpha);
 }
 
 __device__ __forceinline__ const double* wbar_omega_of(const DevPlan& P, double* S, int k, int lev, int64_t idx) {
@@ -103,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
   const double* V0 = gr.Tsum(0, 0);
   for (int l = 0; l < m; ++l) {       // Xbar_l = -2 sum_k V_k S^{k,l} - v_w wbar^l'
     acc_zero(acc);
-    for (int k = 0; k < m; ++k) gemm_S(acc, P, S, V0 + (int64_t)k * TT, k, l, m, i, -2.0, lds);
+    gemm_segs(acc, m, [&](int k) { return seg_S(P, S, V0 + (int64_t)k * TT, k, l, m, i, -2.0); }, lds);
     const double* wb = wbar_omega_of(P, S, l, m, i);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -128,8 +121,10 @@ __global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
   __syncthreads();
   // Pbar = -1/2 (sum_l Xbar_l V_l' + xbar_w v_w' + Lt^{-T} Lt^{-1})
   acc_zero(acc);
-  for (int l = 0; l < m; ++l) gemm<Op::N, Op::T>(acc, gr.G(l), T, V0 + (int64_t)l * TT, T, T, -0.5, lds);
-  gemm<Op::T, Op::N>(acc, po.Lti(), T, po.Lti(), T, T, -0.5, lds);
+  gemm_segs(acc, m + 1, [&](int l) {
+    if (l < m) return seg<Op::N, Op::T>(gr.G(l), T, V0 + (int64_t)l * TT, T, -0.5);
+    return seg<Op::T, Op::N>(po.Lti(), T, po.Lti(), T, -0.5);
+  }, lds);
   const double* xw = gr.wbar_omega();
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -155,15 +150,20 @@ __global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, int64_t t0) {
   const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
   const double* Y = S + P.off_y + cpl * P.plane + poff * T;
   double* V = S + P.off_v + cpl * P.plane + poff * T;
+  const int nR = P.leaf_n[leaf];
   Acc acc;
   for (int ib = nb - 1; ib >= 0; --ib) {
+    const int mr = round16(min(T, nR - T * ib));
     acc_load(acc, Y + (int64_t)ib * TT, T);
-    for (int jb = ib + 1; jb < nb; ++jb)
-      gemm<Op::T, Op::N>(acc, base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, T, -1.0, lds);
+    gemm_segs(acc, nb - 1 - ib, [&](int q) {
+      const int jb = ib + 1 + q;
+      return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
+    }, lds, mr);
     acc_store(acc, V + (int64_t)ib * TT, T);
     __syncthreads();
     acc_zero(acc);
-    gemm<Op::T, Op::N>(acc, dinv + (int64_t)ib * TT, T, V + (int64_t)ib * TT, T, T, 1.0, lds);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, V + (int64_t)ib * TT, T, 1.0); },
+              lds, mr);
     acc_store(acc, V + (int64_t)ib * TT, T);
     __syncthreads();
   }
@@ -187,14 +187,15 @@ __global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, int64_t t0) {
   __syncthreads();
   for (int ib = j + 1; ib < nb; ++ib) {
     acc_zero(acc);
-    for (int kb = j; kb < ib; ++kb)
-      gemm<Op::N, Op::N>(acc, base + ((int64_t)ib * nb + kb) * TT, T, Li + ((int64_t)kb * nb + j) * TT, T, T, -1.0,
-                         lds);
+    gemm_segs(acc, ib - j, [&](int q) {
+      const int kb = j + q;
+      return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + kb) * TT, T, Li + ((int64_t)kb * nb + j) * TT, T, -1.0);
+    }, lds);
     double* out = Li + ((int64_t)ib * nb + j) * TT;
     acc_store(acc, out, T);
     __syncthreads();
     acc_zero(acc);
-    gemm<Op::N, Op::N>(acc, dinv + (int64_t)ib * TT, T, out, T, T, 1.0, lds);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, out, T, 1.0); }, lds);
     acc_store(acc, out, T);
     __syncthreads();
   }
@@ -218,7 +219,9 @@ __global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, int64_t t0) {
   if (c < M) {
     Acc acc;
     acc_zero(acc);
-    for (int k = 0; k < M; ++k) gemm_S(acc, P, S, V + (int64_t)k * P.plane, k, c, M, leaf, 1.0, lds);
+    const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
+    gemm_segs(acc, M, [&](int k) { return seg_S(P, S, V + (int64_t)k * P.plane, k, c, M, leaf, 1.0); }, lds,
+              round16(nx));
     const double* wb = wbar_omega_of(P, S, c, M, leaf);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -264,11 +267,12 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   const double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
   Acc acc;
   acc_zero(acc);
-  for (int c = 0; c <= P.M; ++c)
-    gemm<Op::N, Op::T>(acc, S + P.off_q + c * P.plane + pi * T, T, S + P.off_v + c * P.plane + pj * T, T, T, -1.0,
-                       lds);
-  for (int kb = bi; kb < nb; ++kb)
-    gemm<Op::T, Op::N>(acc, Li + ((int64_t)kb * nb + bi) * TT, T, Li + ((int64_t)kb * nb + bj) * TT, T, T, -0.5, lds);
+  gemm_segs(acc, P.M + 1 + (nb - bi), [&](int q) {
+    if (q <= P.M)
+      return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0);
+    const int kb = bi + q - (P.M + 1);
+    return seg<Op::T, Op::N>(Li + ((int64_t)kb * nb + bi) * TT, T, Li + ((int64_t)kb * nb + bj) * TT, T, -0.5);
+  }, lds);
   double* out = S + P.off_sbar + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT;
   acc_store(acc, out, T);
   if (bi == bj) {
@@ -307,12 +311,10 @@ __global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, int64_t t0) {
   for (int bi2 = 0; bi2 < 2; ++bi2)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc.c[bi2][bj] *= 2.0;
-  for (int bj = 0; bj < nb; ++bj) {
-    if (bj <= bi)
-      gemm<Op::N, Op::N>(acc, Sb + ((int64_t)bi * nb + bj) * TT, T, W + (int64_t)bj * TT, T, T, -2.0, lds);
-    else
-      gemm<Op::T, Op::N>(acc, Sb + ((int64_t)bj * nb + bi) * TT, T, W + (int64_t)bj * TT, T, T, -2.0, lds);
-  }
+  gemm_segs(acc, nb, [&](int bj) {
+    if (bj <= bi) return seg<Op::N, Op::N>(Sb + ((int64_t)bi * nb + bj) * TT, T, W + (int64_t)bj * TT, T, -2.0);
+    return seg<Op::T, Op::N>(Sb + ((int64_t)bj * nb + bi) * TT, T, W + (int64_t)bj * TT, T, -2.0);
+  }, lds, round16(min(T, P.leaf_n[leaf] - T * bi)));
   acc_store(acc, S + P.off_wbar + (int64_t)c * P.plane + p0 * T, T);
 }
 
@@ -322,19 +324,20 @@ __global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, int64_t t0) {
 __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
                                   int64_t bstride, int lev, int64_t idx, double g[3], double* lds) {
   Acc acc;
+  const int mr = round16(nx);
   for (int l = lev - 1; l >= 0; --l) {
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
     double* Rl = rows + l * bstride;
     acc_zero(acc);
-    gemm<Op::N, Op::N>(acc, Rl, T, Pa + (l + 1) * TT, T, T, 1.0, lds);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(Rl, T, Pa + (l + 1) * TT, T, 1.0); }, lds, mr);
     acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
     acc_store(acc, Rl, T);
     __syncthreads();
     for (int k = 0; k < l; ++k) {
       double* Rk = rows + k * bstride;
       acc_load(acc, Rk, T);
-      gemm<Op::N, Op::N>(acc, Rl, T, Pa + (int64_t)k * TT, T, T, -1.0, lds);
+      gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(Rl, T, Pa + (int64_t)k * TT, T, -1.0); }, lds, mr);
       acc_store(acc, Rk, T);
     }
     __syncthreads();
@@ -372,11 +375,22 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, int64_t t0) {
   const double* Wh = S + P.off_wobs + (int64_t)k * P.plane;
   Acc acc;
   acc_zero(acc);
+  int nsg = 0;
   for (int cc = 0; cc < P.J; ++cc) {
     const int64_t leaf = pidx * P.J + cc;
-    for (int64_t p = P.leaf_poff[leaf]; p < P.leaf_poff[leaf + 1]; p += T)
-      gemm<Op::T, Op::N>(acc, Wb + p * T, T, Wh + p * T, T, T, 1.0, lds);
+    nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
+  gemm_segs(acc, nsg, [&](int sg) {
+    int64_t leaf = pidx * P.J;
+    int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
+    while (sg >= nbl) {
+      sg -= nbl;
+      ++leaf;
+      nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
+    }
+    const int64_t p = P.leaf_poff[leaf] + (int64_t)sg * T;
+    return seg<Op::T, Op::N>(Wb + p * T, T, Wh + p * T, T, 1.0, round16(min(T, P.leaf_n[leaf] - T * sg)) / KC);
+  }, lds);
   acc_store(acc, grad_of(P, S, M - 1, pidx).Tsum(l, k), T);
 }
 
@@ -457,12 +471,11 @@ __global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, int64_t t0) {
   double* S = slice(P, th);
   Acc acc;
   acc_zero(acc);
-  for (int cc = 0; cc < P.J; ++cc) {
+  for (int cc = 0; cc < P.J; ++cc) acc_load(acc, grad_of(P, S, m, pidx * P.J + cc).Tsum(l, k), T, true);
+  gemm_segs(acc, P.J, [&](int cc) {
     const int64_t ch = pidx * P.J + cc;
-    Grad gc = grad_of(P, S, m, ch);
-    acc_load(acc, gc.Tsum(l, k), T, true);
-    gemm<Op::T, Op::N>(acc, gc.Wbar(l), T, prior_reg(P, S, m, ch) + (int64_t)k * TT, T, T, 1.0, lds);
-  }
+    return seg<Op::T, Op::N>(grad_of(P, S, m, ch).Wbar(l), T, prior_reg(P, S, m, ch) + (int64_t)k * TT, T, 1.0);
+  }, lds);
   acc_store(acc, grad_of(P, S, m - 1, pidx).Tsum(l, k), T);
 }
 

@@ -54,12 +54,12 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   for (int jb = 0; jb < nb; ++jb) {
     const int64_t pj = poff + (int64_t)T * jb;
     acc_cov(acc, X, nx, P.obs_xy + 2 * pj, min(T, nR - T * jb), c, false, 0.0);
-    for (int k = 0; k < M; ++k)
-      gemm<Op::N, Op::T>(acc, U + (int64_t)k * pplane, T, S + P.off_wobs + (int64_t)k * P.plane + pj * T, T, T, -1.0,
-                         lds);
-    // E_j = (L^M_j - sum_{k<j} E_k L_{j,k}') L_jj^{-T}
-    for (int kb = 0; kb < jb; ++kb)
-      gemm<Op::N, Op::T>(acc, E + (int64_t)kb * TT, T, Lsig + ((int64_t)jb * nb + kb) * TT, T, T, -1.0, lds);
+    // L^M_j, then E_j = (L^M_j - sum_{k<j} E_k L_{j,k}') L_jj^{-T}
+    gemm_segs(acc, M + jb, [&](int q) {
+      if (q < M) return seg<Op::N, Op::T>(U + (int64_t)q * pplane, T, S + P.off_wobs + (int64_t)q * P.plane + pj * T, T, -1.0);
+      const int kb = q - M;
+      return seg<Op::N, Op::T>(E + (int64_t)kb * TT, T, Lsig + ((int64_t)jb * nb + kb) * TT, T, -1.0);
+    }, lds, round16(nx));
     acc_store(acc, E + (int64_t)jb * TT, T);
     __syncthreads();
     acc_zero(acc);
@@ -91,9 +91,10 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   // B~^{M,k} = U^^k - E Y_k (in place over U^^k)
   for (int k = 0; k < M; ++k) {
     acc_load(acc, U + (int64_t)k * pplane, T);
-    for (int jb = 0; jb < nb; ++jb)
-      gemm<Op::N, Op::N>(acc, E + (int64_t)jb * TT, T, S + P.off_y + (int64_t)k * P.plane + (poff + (int64_t)T * jb) * T,
-                         T, T, -1.0, lds);
+    gemm_segs(acc, nb, [&](int jb) {
+      return seg<Op::N, Op::N>(E + (int64_t)jb * TT, T, S + P.off_y + (int64_t)k * P.plane + (poff + (int64_t)T * jb) * T,
+                               T, -1.0);
+    }, lds, round16(nx));
     acc_store(acc, U + (int64_t)k * pplane, T);
   }
   __syncthreads();

@@ -138,6 +138,112 @@ __device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const d
 }
 
 // ---------------------------------------------------------------------------
+// multi-segment GEMM: acc += sum_s alpha_s * opA_s(A_s) * opB_s(B_s), each
+// segment a 64x64xK_s product (K_s = 16 * nch_s, nch_s in 1..4).  The
+// prefetch pipeline of gemm() runs across segment boundaries, so a chain of
+// short products pays the global-memory latency once.  Row blocks of the
+// output at or beyond `mrows` are not multiplied (their operand rows are
+// padding).
+// ---------------------------------------------------------------------------
+struct Seg {
+  const double* A;
+  const double* B;
+  int lda, ldb;
+  bool ak;      // A(i,k) = A[k*lda + i] (k-major) instead of A[i*lda + k]
+  bool bk;      // B(k,j) = B[k*ldb + j] (k-major) instead of B[j*ldb + k]
+  int nch;      // k-chunks of KC
+  double alpha;
+};
+
+__device__ __forceinline__ d4 fetch_rt(const double* p, int ld, int k0, bool kmajor) {
+  const int t = threadIdx.x;
+  if (!kmajor) return *(const d4*)(p + (int64_t)(t >> 2) * ld + k0 + (t & 3) * 4);
+  return *(const d4*)(p + (int64_t)(k0 + (t >> 4)) * ld + (t & 15) * 4);
+}
+__device__ __forceinline__ void stash_rt(double* s, d4 v, bool kmajor) {
+  const int t = threadIdx.x;
+  if (!kmajor) {
+    const int i = t >> 2, kq = (t & 3) * 4;
+    s[(kq + 0) * SLD + i] = v[0];
+    s[(kq + 1) * SLD + i] = v[1];
+    s[(kq + 2) * SLD + i] = v[2];
+    s[(kq + 3) * SLD + i] = v[3];
+  } else {
+    *(d4*)(s + (t >> 4) * SLD + (t & 15) * 4) = v;
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void gemm_segs(Acc& acc, int nseg, F getseg, double* lds, int mrows = T) {
+  if (nseg <= 0) return;
+  const int w = wave_id(), l = lane_id();
+  const int ia = 32 * (w >> 1) + (l & 15);
+  const int jb = 32 * (w & 1) + (l & 15);
+  const int kr = l >> 4;
+  const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
+  int s = 0, cs = 0;
+  Seg cur = getseg(0);
+  d4 va = fetch_rt(cur.A, cur.lda, 0, cur.ak);
+  d4 vb = fetch_rt(cur.B, cur.ldb, 0, cur.bk);
+  stash_rt(lds, va, cur.ak);
+  stash_rt(lds + KC * SLD, vb, cur.bk);
+  __syncthreads();
+  double alpha_c = cur.alpha;
+  int stage = 0;
+  for (;;) {
+    // advance the prefetch position to the next chunk
+    bool more = true;
+    if (cs + 1 < cur.nch) {
+      ++cs;
+    } else if (s + 1 < nseg) {
+      ++s;
+      cs = 0;
+      cur = getseg(s);
+    } else {
+      more = false;
+    }
+    if (more) {
+      va = fetch_rt(cur.A, cur.lda, cs * KC, cur.ak);
+      vb = fetch_rt(cur.B, cur.ldb, cs * KC, cur.bk);
+    }
+    const double* sA = lds + stage * 2 * KC * SLD;
+    const double* sB = sA + KC * SLD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const double* ra = sA + (kk + kr) * SLD;
+      const double* rb = sB + (kk + kr) * SLD;
+      const double b0 = rb[jb], b1 = rb[jb + 16];
+      if (row0) {
+        const double a0 = alpha_c * ra[ia];
+        acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+      }
+      if (row1) {
+        const double a1 = alpha_c * ra[ia + 16];
+        acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+      }
+    }
+    if (!more) {
+      __syncthreads();
+      return;
+    }
+    stage ^= 1;
+    double* nA = lds + stage * 2 * KC * SLD;
+    stash_rt(nA, va, cur.ak);
+    stash_rt(nA + KC * SLD, vb, cur.bk);
+    __syncthreads();
+    alpha_c = cur.alpha;
+  }
+}
+
+// Seg for one 64x64x64 block product in the gemm<> operand conventions
+template <Op OA, Op OB>
+__device__ __forceinline__ Seg seg(const double* A, int lda, const double* B, int ldb, double alpha, int nch = T / KC) {
+  return Seg{A, B, lda, ldb, OA == Op::T, OB == Op::N, nch, alpha};
+}
+
+// ---------------------------------------------------------------------------
 // factorisation of one 64x64 tile in LDS (pitch PLD)
 // ---------------------------------------------------------------------------
 
