@@ -40,10 +40,12 @@ __global__ void k_gather(DevPlan P, const double* y) {
 }
 
 // prior level m < M: one workgroup per region
-__global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, int m, int64_t i0) {
+__global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, int m, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int64_t i = i0 + blockIdx.x;
+  const int64_t i = tk0;
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
   double* reg = prior_reg(P, S, m, i);
@@ -60,10 +62,12 @@ __global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, in
 }
 
 // rows of W^ for the observations of one 64-row leaf tile
-__global__ __launch_bounds__(NT) void k_leaf_rows(DevPlan P, const double* theta, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_leaf_rows(DevPlan P, const double* theta, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int32_t* task = P.row_tasks + 2 * (t0 + blockIdx.x);
+  const int32_t* task = P.row_tasks + 2 * tk0;
   const int leaf = task[0];
   const int64_t p0 = task[1];
   double* S = slice(P, th);
@@ -73,10 +77,12 @@ __global__ __launch_bounds__(NT) void k_leaf_rows(DevPlan P, const double* theta
 }
 
 // Sigma_R = C_0(S_R, S_R) + tau^2 I - W^_R W^_R' per tile (bi >= bj)
-__global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int32_t* task = P.sig_tasks + 3 * (t0 + blockIdx.x);
+  const int32_t* task = P.sig_tasks + 3 * tk0;
   const int leaf = task[0], bi = task[1], bj = task[2];
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
@@ -96,11 +102,13 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, in
 
 // blocked right-looking Cholesky of one leaf's Sigma (tiles in place), the
 // inverses of its diagonal tiles, and d_R = log|Sigma_R|
-__global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int leaf = P.fac_tasks[t0 + blockIdx.x];
+  const int leaf = P.fac_tasks[tk0];
   double* S = slice(P, th);
   const int64_t poff = P.leaf_poff[leaf];
   const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
@@ -143,10 +151,12 @@ __global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, int64_t t0) {
 
 // Y = L_Sigma^{-1} X for one column plane of one leaf (forward substitution
 // by tiles with the inverted diagonal tiles)
-__global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int32_t* task = P.trsm_tasks + 2 * (t0 + blockIdx.x);
+  const int32_t* task = P.trsm_tasks + 2 * tk0;
   const int leaf = task[0], cpl = task[1];
   double* S = slice(P, th);
   const int64_t poff = P.leaf_poff[leaf];
@@ -176,13 +186,15 @@ __global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, int64_t t0) {
 // leaf products summed over the J leaves of a level-(M-1) region
 // (eq. helpquantities at m = M, eq. mainquantities):
 //   A^{k,l} = sum_c Y^k_c' Y^l_c, w^k = sum_c Y^k_c' y_c, u = sum_c y_c'y_c, d = sum_c d_c
-__global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
   const int M = P.M;
   const int nkl = M * (M + 1) / 2;
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t pidx = gid / nkl;
   const int kl = (int)(gid % nkl);
   int k, l;
@@ -242,11 +254,13 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, int64_t t0) {
 
 // posterior level m: K~^{-1} = I + A^{m,m} (whitened), its factor and
 // inverse, Z = Lt^{-1} [A^{m,0..m-1} | w^m], d and u (Sec. 3.3)
-__global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_loglik, int64_t i0) {
+__global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_loglik, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t i = i0 + blockIdx.x;
+  const int64_t i = tk0;
   double* S = slice(P, th);
   Post po = post_of(P, S, m, i);
   tile_to_lds(po.A(m, m), T, lds);
@@ -287,11 +301,13 @@ __global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_logli
 
 // child sums for level m-1 (eq. mainquantities with eq. helpquantities):
 //   A^{k,l}_P = sum_c (A^{k,l}_c - Z^k_c' Z^l_c),  w^k_P = sum_c (w^k_c - Z^k_c' z_c)
-__global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
   const int nkl = m * (m + 1) / 2;       // blocks k >= l <= m-1
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t pidx = gid / nkl;
   const int kl = (int)(gid % nkl);
   int k, l;
@@ -371,14 +387,16 @@ hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* th
   run("leaf_rows", -1, F.leaf_rows, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
   run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
   run("leaf_potrf", -1, F.potrf, k_leaf_potrf, (int64_t)H.fac_tasks.size());
-  run("leaf_trsm", -1, F.trsm, k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
+  run.grouped("leaf_trsm", -1, F.trsm, M + 1, k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
   if (M == 0) {
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
-    run("leaf_reduce", -1, F.leaf_reduce, k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    run.grouped("leaf_reduce", -1, F.leaf_reduce, M * (M + 1) / 2, k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
       run("post", m, F.post[m], k_post, P.nreg[m], m, out_loglik);
-      if (m > 0) run("post_reduce", m, F.post_reduce[m], k_post_reduce, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+      if (m > 0)
+        run.grouped("post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, k_post_reduce,
+                    P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);

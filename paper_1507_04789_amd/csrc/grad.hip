@@ -71,10 +71,12 @@ __device__ void write_partial(const DevPlan& P, double* S, int64_t slot, double 
 
 // ---------------------------------------------------------------- posterior
 // region (m, i), top-down: G^{m,l} = Xbar_l, G^{m,m} = Pbar, wbar^m = xbar_w
-__global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
+__global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int64_t i = i0 + blockIdx.x;
+  const int64_t i = tk0;
   double* S = slice(P, th);
   Post po = post_of(P, S, m, i);
   Grad gr = grad_of(P, S, m, i);
@@ -138,10 +140,12 @@ __global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, int64_t i0) {
 
 // ---------------------------------------------------------------- leaves
 // V = L_Sigma^{-T} Y for one column plane (backward substitution by tiles)
-__global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int32_t* task = P.trsm_tasks + 2 * (t0 + blockIdx.x);
+  const int32_t* task = P.trsm_tasks + 2 * tk0;
   const int leaf = task[0], cpl = task[1];
   double* S = slice(P, th);
   const int64_t poff = P.leaf_poff[leaf];
@@ -170,10 +174,12 @@ __global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, int64_t t0) {
 }
 
 // tile column j of L_Sigma^{-1} (forward substitution of the identity)
-__global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int32_t* task = P.linv_tasks + 2 * (t0 + blockIdx.x);
+  const int32_t* task = P.linv_tasks + 2 * tk0;
   const int leaf = task[0], j = task[1];
   double* S = slice(P, th);
   const int64_t poff = P.leaf_poff[leaf];
@@ -202,11 +208,13 @@ __global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, int64_t t0) {
 }
 
 // Q = V Fbar for one 64-row tile and one column plane c (c = M: the z column)
-__global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
   const int M = P.M;
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t tsk = gid / (M + 1);
   const int c = (int)(gid % (M + 1));
   const int32_t* task = P.row_tasks + 2 * tsk;
@@ -251,11 +259,13 @@ __global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, int64_t t0) {
 
 // Sigma-bar tile (bi, bj) = -sum_c Q_c[bi] V_c[bj]' - 1/2 (Sigma^{-1})_{bi,bj},
 // contracted with the leaf covariance tile
-__global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* theta, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* theta, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t tk = t0 + blockIdx.x;
+  const int64_t tk = tk0;
   const int32_t* task = P.sig_tasks + 3 * tk;
   const int leaf = task[0], bi = task[1], bj = task[2];
   double* S = slice(P, th);
@@ -289,11 +299,13 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
 }
 
 // W^-bar of the leaf rows: 2 Q_c - 2 Sigma-bar W^_c, per row tile and plane c < M
-__global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
   const int M = P.M;
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t tsk = gid / M;
   const int c = (int)(gid % M);
   const int32_t* task = P.row_tasks + 2 * tsk;
@@ -319,8 +331,10 @@ __global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, int64_t t0) {
 }
 
 // Reverse row sweep for 64 rows (points X, nx valid) of a region at level
-// lev: Wbar^l = W^-bar^l L_{a_l}^{-1}, contracted with C_0(X, Q_{a_l});
-// W^-bar^k -= Wbar^l W^^k_{a_l}.  rows + l*bstride hold W^-bar, then Wbar.
+// lev, left-looking: for l = lev-1..0,
+//   W^-bar^l = (initial W^-bar^l) - sum_{l' > l} Wbar^{l'} W^^l_{a_{l'}},
+//   Wbar^l = W^-bar^l L_{a_l}^{-1}, contracted with C_0(X, Q_{a_l}).
+// rows + l*bstride hold the initial W^-bar^l on entry and Wbar^l on return.
 __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
                                   int64_t bstride, int lev, int64_t idx, double g[3], double* lds) {
   Acc acc;
@@ -329,26 +343,29 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
     double* Rl = rows + l * bstride;
+    acc_load(acc, Rl, T);
+    gemm_segs(acc, lev - 1 - l, [&](int q) {
+      const int lp = l + 1 + q;
+      return seg<Op::N, Op::N>(rows + lp * bstride, T, prior_reg(P, S, lp, ancestor(P, lev, idx, lp)) + (int64_t)l * TT,
+                               T, -1.0);
+    }, lds, mr);
+    acc_store(acc, Rl, T);
+    __syncthreads();
     acc_zero(acc);
     gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(Rl, T, Pa + (l + 1) * TT, T, 1.0); }, lds, mr);
     acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
     acc_store(acc, Rl, T);
     __syncthreads();
-    for (int k = 0; k < l; ++k) {
-      double* Rk = rows + k * bstride;
-      acc_load(acc, Rk, T);
-      gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(Rl, T, Pa + (int64_t)k * TT, T, -1.0); }, lds, mr);
-      acc_store(acc, Rk, T);
-    }
-    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(NT) void k_rrows_leaf(DevPlan P, const double* theta, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t tk = t0 + blockIdx.x;
+  const int64_t tk = tk0;
   const int32_t* task = P.row_tasks + 2 * tk;
   const int leaf = task[0];
   const int64_t p0 = task[1];
@@ -361,12 +378,14 @@ __global__ __launch_bounds__(NT) void k_rrows_leaf(DevPlan P, const double* thet
 }
 
 // Tsum^{l,k} of a level-(M-1) region: sum over its leaves' rows of Wbar^l' W^^k
-__global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
   const int M = P.M;
   const int nkl = M * (M + 1) / 2;
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t pidx = gid / nkl;
   int l, k;
   kl_split((int)(gid % nkl), l, k);
@@ -397,11 +416,13 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, int64_t t0) {
 // ---------------------------------------------------------------- prior
 // region (m, i), bottom-up: Cholesky adjoint of L_R, then the reverse row
 // sweep of its knots
-__global__ __launch_bounds__(NT) void k_rprior(DevPlan P, const double* theta, int m, int64_t i0) {
+__global__ __launch_bounds__(NT) void k_rprior(DevPlan P, const double* theta, int m, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t i = i0 + blockIdx.x;
+  const int64_t i = tk0;
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
   Grad gr = grad_of(P, S, m, i);
@@ -460,11 +481,13 @@ __global__ __launch_bounds__(NT) void k_rprior(DevPlan P, const double* theta, i
 
 // Tsum of a level-(m-1) region: sum over children (level m) of
 // Tsum_c^{l,k} + Wbar_c^l' W^^k_c, k <= l <= m-1
-__global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, int64_t t0) {
+__global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
   const int nkl = m * (m + 1) / 2;
-  const int64_t gid = t0 + blockIdx.x;
+  const int64_t gid = tk0;
   const int64_t pidx = gid / nkl;
   int l, k;
   kl_split((int)(gid % nkl), l, k);
@@ -519,17 +542,17 @@ hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
   for (int m = 0; m < M; ++m) run("rpost", m, F.rpost[m], k_rpost, P.nreg[m], m);
-  run("rleaf_v", -1, F.rleaf_v, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
+  run.grouped("rleaf_v", -1, F.rleaf_v, M + 1, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
   run("rleaf_linv", -1, F.rleaf_linv, k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
-  run("rleaf_q", -1, F.rleaf_q, k_rleaf_q, nrow * (M + 1));
+  run.grouped("rleaf_q", -1, F.rleaf_q, M + 1, k_rleaf_q, nrow * (M + 1));
   run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
   if (M > 0) {
-    run("rleaf_wbar", -1, F.rleaf_wbar, k_rleaf_wbar, nrow * M);
+    run.grouped("rleaf_wbar", -1, F.rleaf_wbar, M, k_rleaf_wbar, nrow * M);
     run("rrows_leaf", -1, F.rrows, k_rrows_leaf, nrow, theta);
-    run("rT_leaf", -1, F.rT_leaf, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    run.grouped("rT_leaf", -1, F.rT_leaf, M * (M + 1) / 2, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
       run("rprior", m, F.rprior[m], k_rprior, P.nreg[m], theta, m);
-      if (m > 0) run("rT", m, F.rT[m], k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+      if (m > 0) run.grouped("rT", m, F.rT[m], m * (m + 1) / 2, k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   hipLaunchKernelGGL(k_gsum, dim3(nth), dim3(NT), 0, st, P, theta, out_grad, nslot);

@@ -14,6 +14,27 @@ struct mra_plan_s;
 
 namespace mra {
 
+// Task index of a workgroup.  Batched launches of tasks that share inputs
+// (G consecutive task indices) place each group on one XCD: workgroups are
+// dispatched to the 8 XCDs round-robin by block index, so block b runs on
+// XCD b % 8; group g goes to XCD g % 8, and its G tasks take consecutive
+// slots there, so they find the group's inputs in that XCD's L2.  Blocks
+// past the last group return -1.
+struct TaskMap {
+  int64_t t0;     // first task (plain form: the single task of the launch)
+  int64_t ntask;  // tasks in the launch (a multiple of G when G > 1)
+  int32_t G;      // group size; 1 = identity mapping
+};
+
+__device__ __forceinline__ int64_t task_of(const TaskMap& m) {
+  const int64_t b = blockIdx.x;
+  if (m.G <= 1) return m.t0 + b;
+  const int64_t xcd = b & 7, s = b >> 3;
+  const int64_t g = (s / m.G) * 8 + xcd;
+  if (g * m.G >= m.ntask) return -1;
+  return g * m.G + (s % m.G);
+}
+
 struct ProfRecord {
   const char* name;
   int level;
@@ -48,6 +69,10 @@ struct Runner {
   Profiler* prof;
   template <class K, class... A>
   void operator()(const char* name, int level, double flops, K kern, int64_t ntask, A... args) const {
+    grouped(name, level, flops, 1, kern, ntask, args...);
+  }
+  template <class K, class... A>
+  void grouped(const char* name, int level, double flops, int G, K kern, int64_t ntask, A... args) const {
     if (ntask <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof && prof->enabled) {
@@ -57,9 +82,13 @@ struct Runner {
     }
     if (plain) {
       for (int64_t t = 0; t < ntask; ++t)
-        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., t);
+        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., TaskMap{t, ntask, 1});
+    } else if (G <= 1) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., TaskMap{0, ntask, 1});
     } else {
-      hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., (int64_t)0);
+      const int64_t ngroups = ntask / G;
+      const int64_t nblk = (ngroups + 7) / 8 * 8 * G;
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, nth), dim3(256), 0, st, P, args..., TaskMap{0, ntask, G});
     }
     if (e0 && e1) {
       (void)hipEventRecord(e1, st);

@@ -28,10 +28,12 @@ __device__ __forceinline__ double row_dot(const double* a, const double* b) {
 
 // one 64-row prediction tile
 __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, double* mean, double* var,
-                                                int64_t t0) {
+                                                TaskMap tm) {
+  const int64_t tk0 = task_of(tm);
+  if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double mu[T], vv[T];
-  const int64_t tk = t0 + blockIdx.x;
+  const int64_t tk = tk0;
   const int32_t* task = P.pred_tasks + 2 * tk;
   const int leaf = task[0];
   const int64_t q0 = task[1];
