@@ -11,7 +11,6 @@
 
 namespace mra {
 
-hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st);
 hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st);
 
 namespace {
@@ -38,6 +37,37 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
     }
   }
   return MRA_OK;
+}
+
+// forward + reverse.  The reverse pass's leaf solves only need the forward
+// leaf factors, so they run on a second stream (default priority) while the
+// posterior recursion and its reverse proceed on the caller's stream.
+hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
+                           hipStream_t st) {
+  hipError_t e = launch_forward_front(*H, y, theta, nth, st);
+  if (e != hipSuccess) return e;
+  const bool overlap = !(H->cfg.flags & MRA_PLAIN);
+  if (overlap && !H->side_stream) {
+    hipStream_t s2;
+    hipEvent_t a, b;
+    if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) return e;
+    H->side_stream = s2;
+    H->ev_fork = a;
+    H->ev_join = b;
+  }
+  hipStream_t s2 = overlap ? (hipStream_t)H->side_stream : st;
+  if (overlap) {
+    if ((e = hipEventRecord((hipEvent_t)H->ev_fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, (hipEvent_t)H->ev_fork, 0)) != hipSuccess) return e;
+  }
+  if ((e = launch_grad_leafsolve(*H, nth, s2)) != hipSuccess) return e;
+  if (overlap && (e = hipEventRecord((hipEvent_t)H->ev_join, s2)) != hipSuccess) return e;
+  if ((e = launch_forward_back(*H, nth, ll, st)) != hipSuccess) return e;
+  if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
+  if (overlap && (e = hipStreamWaitEvent(st, (hipEvent_t)H->ev_join, 0)) != hipSuccess) return e;
+  return launch_grad_rest(*H, theta, nth, g, st);
 }
 
 mra_status check_call(const mra_plan_s* H, int nth) {
@@ -178,9 +208,7 @@ mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_thet
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
-  s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
-  if (s != MRA_OK) return s;
-  s = check_hip(launch_grad(*P, d_theta, n_theta, d_grad, st));
+  s = check_hip(launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, st));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
   return MRA_OK;
@@ -276,6 +304,12 @@ const char* mra_status_string(mra_status s) {
 
 void mra_destroy(mra_plan_t P) {
   if (!P) return;
+  if (P->side_stream) {
+    (void)hipStreamSynchronize((hipStream_t)P->side_stream);
+    (void)hipStreamDestroy((hipStream_t)P->side_stream);
+  }
+  if (P->ev_fork) (void)hipEventDestroy((hipEvent_t)P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy((hipEvent_t)P->ev_join);
   delete P->prof;
   delete P;
 }

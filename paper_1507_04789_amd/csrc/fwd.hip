@@ -373,8 +373,9 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 }
 
 // ------------------------------------------------------------------ launches
-hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
-                          hipStream_t st) {
+// init, prior levels and the leaf factorisation (everything the reverse
+// pass's leaf solves depend on)
+hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -388,6 +389,15 @@ hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* th
   run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
   run("leaf_potrf", -1, F.potrf, k_leaf_potrf, (int64_t)H.fac_tasks.size());
   run.grouped("leaf_trsm", -1, F.trsm, M + 1, k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
+  return hipGetLastError();
+}
+
+// leaf products, posterior recursion and the log-likelihood
+hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st) {
+  const DevPlan& P = H.dp;
+  const PhaseFlops& F = H.pf;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
   if (M == 0) {
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
@@ -401,6 +411,13 @@ hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* th
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);
   return hipGetLastError();
+}
+
+hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
+                          hipStream_t st) {
+  hipError_t e = launch_forward_front(H, y, theta, nth, st);
+  if (e != hipSuccess) return e;
+  return launch_forward_back(H, nth, out_loglik, st);
 }
 
 }  // namespace mra

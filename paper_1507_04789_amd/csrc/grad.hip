@@ -533,7 +533,21 @@ __global__ void k_zero_gpart(DevPlan P, int64_t nslot) {
     S[P.off_gpart + q] = 0.0;
 }
 
-hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st) {
+// leaf solves of the reverse pass that only need the forward leaf factors:
+// V = L_Sigma^{-T} Y and L_Sigma^{-1}; may run on a second stream while the
+// posterior recursion proceeds
+hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st) {
+  const DevPlan& P = H.dp;
+  const PhaseFlops& F = H.pf;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  run.grouped("rleaf_v", -1, F.rleaf_v, M + 1, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
+  run("rleaf_linv", -1, F.rleaf_linv, k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
+  return hipGetLastError();
+}
+
+// the posterior reverse pass (after the forward log-likelihood)
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -542,8 +556,17 @@ hipError_t launch_grad(const mra_plan_s& H, const double* theta, int nth, double
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
   for (int m = 0; m < M; ++m) run("rpost", m, F.rpost[m], k_rpost, P.nreg[m], m);
-  run.grouped("rleaf_v", -1, F.rleaf_v, M + 1, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
-  run("rleaf_linv", -1, F.rleaf_linv, k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
+  return hipGetLastError();
+}
+
+// the leaf and prior reverse passes and the final sum (after both of the above)
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st) {
+  const DevPlan& P = H.dp;
+  const PhaseFlops& F = H.pf;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
+  const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   run.grouped("rleaf_q", -1, F.rleaf_q, M + 1, k_rleaf_q, nrow * (M + 1));
   run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
   if (M > 0) {

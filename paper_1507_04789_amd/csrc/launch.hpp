@@ -99,5 +99,10 @@ struct Runner {
 
 hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
                           hipStream_t st);
+hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st);
+hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st);
+hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st);
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st);
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st);
 
 }  // namespace mra

@@ -70,6 +70,9 @@ struct mra_plan_s {
   mra::GraphCache* graphs = nullptr;
   mra::PhaseFlops pf;
   mra::Profiler* prof = nullptr;
+  void* side_stream = nullptr;   // hipStream_t for work overlapped with the main stream
+  void* ev_fork = nullptr;       // hipEvent_t
+  void* ev_join = nullptr;
   int32_t last_nth = 1;
 };
 
