@@ -42,21 +42,30 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
 // forward + reverse.  The reverse pass's leaf solves only need the forward
 // leaf factors, so they run on a second stream (default priority) while the
 // posterior recursion and its reverse proceed on the caller's stream.
+hipError_t ensure_side(mra_plan_s* H) {
+  if (H->side_stream) return hipSuccess;
+  hipStream_t s2;
+  hipEvent_t a, b;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) return e;
+  H->side_stream = s2;
+  H->ev_fork = a;
+  H->ev_join = b;
+  return hipSuccess;
+}
+
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
                            hipStream_t st) {
-  hipError_t e = launch_forward_front(*H, y, theta, nth, st);
-  if (e != hipSuccess) return e;
   const bool overlap = !(H->cfg.flags & MRA_PLAIN);
-  if (overlap && !H->side_stream) {
-    hipStream_t s2;
-    hipEvent_t a, b;
-    if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) return e;
-    H->side_stream = s2;
-    H->ev_fork = a;
-    H->ev_join = b;
-  }
+  hipError_t e;
+  if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
+  if (overlap)
+    e = launch_forward_front(*H, y, theta, nth, st, (hipStream_t)H->side_stream, H->ev_fork, H->ev_join);
+  else
+    e = launch_forward_front(*H, y, theta, nth, st);
+  if (e != hipSuccess) return e;
   hipStream_t s2 = overlap ? (hipStream_t)H->side_stream : st;
   if (overlap) {
     if ((e = hipEventRecord((hipEvent_t)H->ev_fork, st)) != hipSuccess) return e;
@@ -195,7 +204,16 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   if (!d_y || !d_theta || !d_loglik) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
-  s = check_hip(launch_forward(*P, d_y, d_theta, n_theta, d_loglik, st));
+  if (!(P->cfg.flags & MRA_PLAIN)) {
+    s = check_hip(ensure_side(P));
+    if (s != MRA_OK) return s;
+    s = check_hip(launch_forward_front(*P, d_y, d_theta, n_theta, st, (hipStream_t)P->side_stream, P->ev_fork,
+                                       P->ev_join));
+  } else {
+    s = check_hip(launch_forward_front(*P, d_y, d_theta, n_theta, st));
+  }
+  if (s != MRA_OK) return s;
+  s = check_hip(launch_forward_back(*P, n_theta, d_loglik, st));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
   return MRA_OK;

@@ -40,7 +40,7 @@ __global__ void k_gather(DevPlan P, const double* y) {
 }
 
 // prior level m < M: one workgroup per region
-__global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(NT) void k_prior(DevPlan P, const double* theta, in
 }
 
 // rows of W^ for the observations of one 64-row leaf tile
-__global__ __launch_bounds__(NT) void k_leaf_rows(DevPlan P, const double* theta, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_leaf_rows(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, Ta
 
 // blocked right-looking Cholesky of one leaf's Sigma (tiles in place), the
 // inverses of its diagonal tiles, and d_R = log|Sigma_R|
-__global__ __launch_bounds__(NT) void k_leaf_potrf(DevPlan P, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
 
 // posterior level m: K~^{-1} = I + A^{m,m} (whitened), its factor and
 // inverse, Z = Lt^{-1} [A^{m,0..m-1} | w^m], d and u (Sec. 3.3)
-__global__ __launch_bounds__(NT) void k_post(DevPlan P, int m, double* out_loglik, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_loglik, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -375,7 +375,11 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 // ------------------------------------------------------------------ launches
 // init, prior levels and the leaf factorisation (everything the reverse
 // pass's leaf solves depend on)
-hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st) {
+// With a side stream, the few leaves of three or more tiles are factored and
+// solved there while the many small leaves proceed on `st`; `st` waits for
+// them before returning (the leaf products need every leaf).
+hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
+                                hipStream_t side, void* ev_fork, void* ev_join) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -387,8 +391,23 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   for (int m = 0; m < M; ++m) run("prior", m, F.prior[m], k_prior, P.nreg[m], theta, m);
   run("leaf_rows", -1, F.leaf_rows, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
   run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
-  run("leaf_potrf", -1, F.potrf, k_leaf_potrf, (int64_t)H.fac_tasks.size());
-  run.grouped("leaf_trsm", -1, F.trsm, M + 1, k_leaf_trsm, (int64_t)H.trsm_tasks.size() / 2);
+  const int64_t nfac = (int64_t)H.fac_tasks.size(), ntrsm = (int64_t)H.trsm_tasks.size() / 2;
+  const int64_t nbig = (side && H.n_fac_big > 0) ? H.n_fac_big : 0;
+  if (nbig > 0) {
+    hipError_t e;
+    if ((e = hipEventRecord((hipEvent_t)ev_fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side, (hipEvent_t)ev_fork, 0)) != hipSuccess) return e;
+    Runner rs{P, nth, side, false, H.prof};
+    rs.range("leaf_potrf_big", -1, F.potrf_big, 1, k_leaf_potrf, 0, nbig);
+    rs.range("leaf_trsm_big", -1, F.trsm_big, M + 1, k_leaf_trsm, 0, nbig * (M + 1));
+    if ((e = hipEventRecord((hipEvent_t)ev_join, side)) != hipSuccess) return e;
+  }
+  run.range("leaf_potrf", -1, F.potrf - (nbig ? F.potrf_big : 0.0), 1, k_leaf_potrf, nbig, nfac);
+  run.range("leaf_trsm", -1, F.trsm - (nbig ? F.trsm_big : 0.0), M + 1, k_leaf_trsm, nbig * (M + 1), ntrsm);
+  if (nbig > 0) {
+    hipError_t e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -359,7 +359,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
   }
 }
 
-__global__ __launch_bounds__(NT) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
 // ---------------------------------------------------------------- prior
 // region (m, i), bottom-up: Cholesky adjoint of L_R, then the reverse row
 // sweep of its knots
-__global__ __launch_bounds__(NT) void k_rprior(DevPlan P, const double* theta, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];

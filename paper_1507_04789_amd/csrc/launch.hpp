@@ -32,7 +32,7 @@ __device__ __forceinline__ int64_t task_of(const TaskMap& m) {
   const int64_t xcd = b & 7, s = b >> 3;
   const int64_t g = (s / m.G) * 8 + xcd;
   if (g * m.G >= m.ntask) return -1;
-  return g * m.G + (s % m.G);
+  return m.t0 + g * m.G + (s % m.G);
 }
 
 struct ProfRecord {
@@ -73,6 +73,12 @@ struct Runner {
   }
   template <class K, class... A>
   void grouped(const char* name, int level, double flops, int G, K kern, int64_t ntask, A... args) const {
+    range(name, level, flops, G, kern, 0, ntask, args...);
+  }
+  // tasks [t_begin, t_end) of a task list
+  template <class K, class... A>
+  void range(const char* name, int level, double flops, int G, K kern, int64_t t_begin, int64_t t_end, A... args) const {
+    const int64_t ntask = t_end - t_begin;
     if (ntask <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof && prof->enabled) {
@@ -81,14 +87,14 @@ struct Runner {
       if (e0) (void)hipEventRecord(e0, st);
     }
     if (plain) {
-      for (int64_t t = 0; t < ntask; ++t)
-        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., TaskMap{t, ntask, 1});
+      for (int64_t t = t_begin; t < t_end; ++t)
+        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., TaskMap{t, 1, 1});
     } else if (G <= 1) {
-      hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., TaskMap{0, ntask, 1});
+      hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., TaskMap{t_begin, ntask, 1});
     } else {
       const int64_t ngroups = ntask / G;
       const int64_t nblk = (ngroups + 7) / 8 * 8 * G;
-      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, nth), dim3(256), 0, st, P, args..., TaskMap{0, ntask, G});
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, nth), dim3(256), 0, st, P, args..., TaskMap{t_begin, ntask, G});
     }
     if (e0 && e1) {
       (void)hipEventRecord(e1, st);
@@ -99,7 +105,8 @@ struct Runner {
 
 hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
                           hipStream_t st);
-hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st);
+hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
+                                hipStream_t side = nullptr, void* ev_fork = nullptr, void* ev_join = nullptr);
 hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st);
 hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st);
 hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st);

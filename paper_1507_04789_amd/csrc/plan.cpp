@@ -201,12 +201,14 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return P->leaf_n[x] > P->leaf_n[y]; });
+  P->n_fac_big = 0;
   P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->linv_tasks.clear();
   P->pred_tasks.clear();
   for (int32_t i : order) {
     int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
     if (nb == 0) continue;
     P->fac_tasks.push_back(i);
+    if (nb >= 3) ++P->n_fac_big;
     for (int64_t t = 0; t < nb; ++t) { P->row_tasks.push_back(i); P->row_tasks.push_back((int32_t)(P->leaf_poff[i] + t * T)); }
     for (int64_t bi = 0; bi < nb; ++bi)
       for (int64_t bj = 0; bj <= bi; ++bj) {
@@ -328,6 +330,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     F.sigma += nr * nr * Mr;                                   // Sigma_R (SYRK)
     F.potrf += nr * nr * nr / 3.0;
     F.trsm += nr * nr * (Mr + 1);                              // L^{-1} [W^ | z]
+    if (nr > 2 * T) {
+      F.potrf_big += nr * nr * nr / 3.0;
+      F.trsm_big += nr * nr * (Mr + 1);
+    }
     F.leaf_reduce += nr * (Mr + 1) * (Mr + 1);                 // [W^ | z]' Sigma^{-1} [W^ | z]
     F.rleaf_v += nr * nr * (Mr + 1);                           // L^{-T} Y
     F.rleaf_linv += nr * nr * nr / 3.0;                        // L^{-1}

@@ -19,6 +19,7 @@ struct Profiler;    // defined in launch.hpp
 struct PhaseFlops {
   double prior[MAXL], post[MAXL], post_reduce[MAXL];
   double leaf_rows, sigma, potrf, trsm, leaf_reduce;
+  double potrf_big, trsm_big;   // part of potrf / trsm in leaves of >= 3 tiles
   double rpost[MAXL], rprior[MAXL], rT[MAXL];
   double rleaf_v, rleaf_linv, rleaf_q, rleaf_sbar, rleaf_wbar, rrows, rT_leaf;
   double predict;
@@ -57,6 +58,7 @@ struct mra_plan_s {
   std::vector<int64_t> pred_gidx;
   // task lists
   std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, linv_tasks, pred_tasks;
+  int64_t n_fac_big = 0;   // leading fac_tasks (and M+1 trsm_tasks each) of leaves with >= 3 tiles
   // layout
   mra::Layout lay;
   mra::DevPlan dp;

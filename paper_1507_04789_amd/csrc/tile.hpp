@@ -342,33 +342,48 @@ __device__ __forceinline__ void blk_load(d4& acc, const double* C, int ldc) {
   for (int v = 0; v < 4; ++v) acc[v] = C[(4 * v + (l >> 4)) * ldc + (l & 15)];
 }
 
+// 1/sqrt(p) to full FP64 precision: the hardware estimate refined by two
+// Newton steps y <- y (3 - p y^2) / 2
+__device__ __forceinline__ double rsqrt_d(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+  y = y * fma(-0.5 * p, y * y, 1.5);
+  y = y * fma(-0.5 * p, y * y, 1.5);
+  return y;
+}
+
 // Lower Cholesky of the 16x16 block D (pitch PLD) in place, left-looking, by
-// lanes 0..15 of one wave (lane i owns row i); upper part zeroed.  Returns
-// 1 if every pivot was positive (uniform over the wave).
-__device__ __forceinline__ int potrf16(double* D) {
+// lanes 0..15 of one wave: lane i keeps row i in registers; row j of the
+// factor is read back from LDS as a broadcast (a wave's LDS accesses complete
+// in order, so column j is visible to every lane in the next step).  rdiag[j]
+// receives 1/L_jj.  Upper part zeroed.  Returns 1 if every pivot was positive
+// (uniform over the wave).
+__device__ __forceinline__ int potrf16(double* D, double* rdiag) {
   const int i = lane_id();
+  const bool own = i < 16;
+  double row[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) row[k] = own ? D[i * PLD + k] : 0.0;
   int ok = 1;
+#pragma unroll
   for (int j = 0; j < 16; ++j) {
-    double a = 0.0;
-    if (i < 16) {
-      const double* ri = D + i * PLD;
-      const double* rj = D + j * PLD;
-      a = ri[j];
-      for (int k = 0; k < j; ++k) a = fma(-ri[k], rj[k], a);
-    }
+    double a = row[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) a = fma(-row[k], D[j * PLD + k], a);
     const double p = readlane_d(a, j);
     ok &= (p > 0.0) ? 1 : 0;
-    const double d = (p > 0.0) ? sqrt(p) : __builtin_nan("");
-    const double inv = 1.0 / d;
-    if (i < 16) D[i * PLD + j] = (i > j) ? a * inv : (i == j ? d : 0.0);
+    const double y = (p > 0.0) ? rsqrt_d(p) : __builtin_nan("");
+    row[j] = (i > j) ? a * y : (i == j ? p * y : 0.0);
+    if (own) D[i * PLD + j] = row[j];
+    if (i == j) rdiag[j] = y;
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
   }
   return ok;
 }
 
 // X (pitch ldx) = inverse of the lower-triangular 16x16 block D (pitch PLD),
-// by lanes 0..15 of one wave (lane j computes column j)
-__device__ __forceinline__ void trtri16(const double* D, double* X, int ldx) {
+// by lanes 0..15 of one wave (lane j computes column j); rdiag = 1/diag(D)
+__device__ __forceinline__ void trtri16(const double* D, const double* rdiag, double* X, int ldx) {
   const int j = lane_id();
   if (j < 16) {
     double x[16];
@@ -377,8 +392,8 @@ __device__ __forceinline__ void trtri16(const double* D, double* X, int ldx) {
       double acc = (r == j) ? 1.0 : 0.0;
 #pragma unroll
       for (int k = 0; k < r; ++k) acc = fma(-D[r * PLD + k], x[k], acc);
-      x[r] = acc / D[r * PLD + r];
-      __builtin_amdgcn_sched_barrier(0);   // keep each row's loads next to their use
+      x[r] = acc * rdiag[r];
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) X[r * ldx + j] = x[r];
@@ -395,6 +410,7 @@ __device__ __forceinline__ void trtri16(const double* D, double* X, int ldx) {
 // inverse then carry NaN.
 __device__ inline bool potrf_trtri(double* s, double* Linv) {
   __shared__ int ok_all;
+  __shared__ double rdiag[T];
   const int w = wave_id();
   if (threadIdx.x == 0) ok_all = 1;
   __syncthreads();
@@ -402,9 +418,9 @@ __device__ inline bool potrf_trtri(double* s, double* Linv) {
     double* Dk = s + 16 * kb * PLD + 16 * kb;
     double* Xk = Linv + 16 * kb * T + 16 * kb;
     if (w == 0) {
-      const int ok = potrf16(Dk);
+      const int ok = potrf16(Dk, rdiag + 16 * kb);
       if (lane_id() == 0 && !ok) ok_all = 0;
-      trtri16(Dk, Xk, T);
+      trtri16(Dk, rdiag + 16 * kb, Xk, T);
     }
     __syncthreads();
     const int ib = kb + 1 + w;                 // panel: L_ik = A_ik X_kk^T
