@@ -44,6 +44,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double lds_x[T * PLD];
   const int th = blockIdx.y;
   const int64_t i = tk0;
   double* S = slice(P, th);
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
             round16(P.r));
   acc_to_lds(acc, lds);
   __syncthreads();
-  if (!potrf_trtri(lds, reg + (m + 1) * TT) && threadIdx.x == 0) record_failure(P, S, m, i);
+  if (!potrf_trtri(lds, lds_x, reg + (m + 1) * TT) && threadIdx.x == 0) record_failure(P, S, m, i);
   lds_to_global(lds, reg + m * TT);
 }
 
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double lds_x[T * PLD];
   __shared__ double red[8];
   const int th = blockIdx.y;
   const int leaf = P.fac_tasks[tk0];
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
     double* Dk = base + ((int64_t)kb * nb + kb) * TT;
     tile_to_lds(Dk, T, lds);
     __syncthreads();
-    ok = potrf_trtri(lds, dinv + (int64_t)kb * TT) && ok;
+    ok = potrf_trtri(lds, lds_x, dinv + (int64_t)kb * TT) && ok;
     logdet += 2.0 * logdiag_lds(lds, min(T, nR - kb * T), red);
     lds_to_global(lds, Dk);
     __syncthreads();
@@ -258,6 +260,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ double lds_x[T * PLD];
   __shared__ double red[8];
   const int th = blockIdx.y;
   const int64_t i = tk0;
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   __syncthreads();
   if (threadIdx.x < T) lds[threadIdx.x * PLD + threadIdx.x] += 1.0;
   __syncthreads();
-  const bool ok = potrf_trtri(lds, po.Lti());
+  const bool ok = potrf_trtri(lds, lds_x, po.Lti());
   const double ld = 2.0 * logdiag_lds(lds, T, red);
   lds_to_global(lds, po.Lt());
   __syncthreads();

@@ -298,54 +298,27 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   write_partial(P, S, tk, g, red);
 }
 
-// W^-bar of the leaf rows: 2 Q_c - 2 Sigma-bar W^_c, per row tile and plane c < M
-__global__ __launch_bounds__(NT) void k_rleaf_wbar(DevPlan P, TaskMap tm) {
-  const int64_t tk0 = task_of(tm);
-  if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
-  const int th = blockIdx.y;
-  const int M = P.M;
-  const int64_t gid = tk0;
-  const int64_t tsk = gid / M;
-  const int c = (int)(gid % M);
-  const int32_t* task = P.row_tasks + 2 * tsk;
-  const int leaf = task[0];
-  const int64_t p0 = task[1];
-  double* S = slice(P, th);
-  const int64_t poff = P.leaf_poff[leaf];
-  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
-  const int bi = (int)((p0 - poff) / T);
-  const double* Sb = S + P.off_sbar + P.leaf_soff[leaf] * TT;
-  const double* W = S + P.off_wobs + (int64_t)c * P.plane + poff * T;
-  Acc acc;
-  acc_load(acc, S + P.off_q + (int64_t)c * P.plane + p0 * T, T);
-#pragma unroll
-  for (int bi2 = 0; bi2 < 2; ++bi2)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc.c[bi2][bj] *= 2.0;
-  gemm_segs(acc, nb, [&](int bj) {
-    if (bj <= bi) return seg<Op::N, Op::N>(Sb + ((int64_t)bi * nb + bj) * TT, T, W + (int64_t)bj * TT, T, -2.0);
-    return seg<Op::T, Op::N>(Sb + ((int64_t)bj * nb + bi) * TT, T, W + (int64_t)bj * TT, T, -2.0);
-  }, lds, round16(min(T, P.leaf_n[leaf] - T * bi)));
-  acc_store(acc, S + P.off_wbar + (int64_t)c * P.plane + p0 * T, T);
-}
-
 // Reverse row sweep for 64 rows (points X, nx valid) of a region at level
 // lev, left-looking: for l = lev-1..0,
-//   W^-bar^l = (initial W^-bar^l) - sum_{l' > l} Wbar^{l'} W^^l_{a_{l'}},
-//   Wbar^l = W^-bar^l L_{a_l}^{-1}, contracted with C_0(X, Q_{a_l}).
-// rows + l*bstride hold the initial W^-bar^l on entry and Wbar^l on return.
+//   W^-bar^l = init_l + extra_l - sum_{l' > l} Wbar^{l'} W^^l_{a_{l'}},
+//   Wbar^l = W^-bar^l L_{a_l}^{-1}, contracted with C_0(X, Q_{a_l}),
+// where init(acc, l) loads the cotangent of W^^l from outside the prior
+// recursion and extra(l, q), q < nextra, adds further product segments to
+// it.  rows + l*bstride receive Wbar^l.
+template <class Init, class Extra>
 __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
-                                  int64_t bstride, int lev, int64_t idx, double g[3], double* lds) {
+                                  int64_t bstride, int lev, int64_t idx, double g[3], double* lds, Init init,
+                                  int nextra, Extra extra) {
   Acc acc;
   const int mr = round16(nx);
   for (int l = lev - 1; l >= 0; --l) {
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
     double* Rl = rows + l * bstride;
-    acc_load(acc, Rl, T);
-    gemm_segs(acc, lev - 1 - l, [&](int q) {
-      const int lp = l + 1 + q;
+    init(acc, l);
+    gemm_segs(acc, nextra + lev - 1 - l, [&](int q) {
+      if (q < nextra) return extra(l, q);
+      const int lp = l + 1 + (q - nextra);
       return seg<Op::N, Op::N>(rows + lp * bstride, T, prior_reg(P, S, lp, ancestor(P, lev, idx, lp)) + (int64_t)l * TT,
                                T, -1.0);
     }, lds, mr);
@@ -359,6 +332,8 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
   }
 }
 
+// leaf rows: the cotangent of W^_R from the leaf step is 2 Q - 2 Sigma-bar W^_R
+// (computed here as the first product segments), then the reverse sweep
 __global__ __launch_bounds__(NT, 2) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
@@ -371,9 +346,26 @@ __global__ __launch_bounds__(NT, 2) void k_rrows_leaf(DevPlan P, const double* t
   const int64_t p0 = task[1];
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
-  const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
+  const int64_t poff = P.leaf_poff[leaf];
+  const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
+  const int bi = (int)((p0 - poff) / T);
+  const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - poff)));
+  const double* Sb = S + P.off_sbar + P.leaf_soff[leaf] * TT;
   double g[3] = {0.0, 0.0, 0.0};
-  row_sweep_reverse(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wbar + p0 * T, P.plane, P.M, leaf, g, lds);
+  auto init = [&](Acc& acc, int l) {
+    acc_load(acc, S + P.off_q + (int64_t)l * P.plane + p0 * T, T);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc.c[a][b] *= 2.0;
+  };
+  auto extra = [&](int l, int bj) {
+    const double* W = S + P.off_wobs + (int64_t)l * P.plane + (poff + (int64_t)bj * T) * T;
+    if (bj <= bi) return seg<Op::N, Op::N>(Sb + ((int64_t)bi * nb + bj) * TT, T, W, T, -2.0);
+    return seg<Op::T, Op::N>(Sb + ((int64_t)bj * nb + bi) * TT, T, W, T, -2.0);
+  };
+  row_sweep_reverse(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wbar + p0 * T, P.plane, P.M, leaf, g, lds, init, nb,
+                    extra);
   write_partial(P, S, P.n_sig_tasks + tk, g, red);
 }
 
@@ -475,7 +467,8 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
     acc_store(acc, gr.Wbar(k), T);
   }
   __syncthreads();
-  row_sweep_reverse(P, S, c, X, P.r, gr.Wbar(0), TT, m, i, g, lds);
+  row_sweep_reverse(P, S, c, X, P.r, gr.Wbar(0), TT, m, i, g, lds, [&](Acc& acc, int l) { acc_load(acc, gr.Wbar(l), T); },
+                    0, [&](int, int) { return Seg{}; });
   write_partial(P, S, P.n_sig_tasks + P.n_row_tasks + P.reg_base[m] + i, g, red);
 }
 
@@ -570,8 +563,7 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, d
   run.grouped("rleaf_q", -1, F.rleaf_q, M + 1, k_rleaf_q, nrow * (M + 1));
   run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
   if (M > 0) {
-    run.grouped("rleaf_wbar", -1, F.rleaf_wbar, M, k_rleaf_wbar, nrow * M);
-    run("rrows_leaf", -1, F.rrows, k_rrows_leaf, nrow, theta);
+    run("rrows_leaf", -1, F.rrows + F.rleaf_wbar, k_rrows_leaf, nrow, theta);
     run.grouped("rT_leaf", -1, F.rT_leaf, M * (M + 1) / 2, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
       run("rprior", m, F.rprior[m], k_rprior, P.nreg[m], theta, m);

@@ -401,33 +401,35 @@ __device__ __forceinline__ void trtri16(const double* D, const double* rdiag, do
 }
 
 // Blocked lower Cholesky of the symmetric 64x64 tile in s (lower triangle
-// read; 4x4 blocks of 16) and the inverse of the factor, Linv (global, ld T).
+// read; 4x4 blocks of 16) and the inverse of the factor, built in the LDS
+// tile sx (pitch PLD) and written to Linv (global, ld T) at the end.
 // Diagonal blocks are factored and inverted by wave 0; panel and trailing
 // updates and the off-diagonal blocks of the inverse
 //   X_ii = L_ii^{-1},  X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj  (i > j)
 // run on MFMA across the four waves.  On return s holds L (upper part zero).
 // Returns false (uniformly) if a pivot was not positive; the factor and the
 // inverse then carry NaN.
-__device__ inline bool potrf_trtri(double* s, double* Linv) {
+__device__ inline bool potrf_trtri(double* s, double* sx, double* Linv) {
   __shared__ int ok_all;
   __shared__ double rdiag[T];
   const int w = wave_id();
   if (threadIdx.x == 0) ok_all = 1;
+  for (int e = threadIdx.x; e < TT; e += NT) sx[(e >> 6) * PLD + (e & 63)] = 0.0;
   __syncthreads();
   for (int kb = 0; kb < 4; ++kb) {
     double* Dk = s + 16 * kb * PLD + 16 * kb;
-    double* Xk = Linv + 16 * kb * T + 16 * kb;
+    double* Xk = sx + 16 * kb * PLD + 16 * kb;
     if (w == 0) {
       const int ok = potrf16(Dk, rdiag + 16 * kb);
       if (lane_id() == 0 && !ok) ok_all = 0;
-      trtri16(Dk, rdiag + 16 * kb, Xk, T);
+      trtri16(Dk, rdiag + 16 * kb, Xk, PLD);
     }
     __syncthreads();
     const int ib = kb + 1 + w;                 // panel: L_ik = A_ik X_kk^T
     if (ib < 4) {
       double* Aik = s + 16 * ib * PLD + 16 * kb;
       d4 acc = {0.0, 0.0, 0.0, 0.0};
-      mfma_abt(acc, Aik, PLD, Xk, T, 16, 1.0);
+      mfma_abt(acc, Aik, PLD, Xk, PLD, 16, 1.0);
       blk_store(acc, Aik, PLD);
     }
     __syncthreads();
@@ -443,30 +445,30 @@ __device__ inline bool potrf_trtri(double* s, double* Linv) {
         }
     __syncthreads();
   }
-  // zero the strictly upper blocks of L and of its inverse
+  // zero the strictly upper blocks of L
   for (int e = threadIdx.x; e < TT; e += NT) {
     const int i = e >> 6, j = e & 63;
-    if ((j >> 4) > (i >> 4)) {
-      s[i * PLD + j] = 0.0;
-      Linv[e] = 0.0;
-    }
+    if ((j >> 4) > (i >> 4)) s[i * PLD + j] = 0.0;
   }
   for (int ib = 1; ib < 4; ++ib) {
     const int jb = w;
-    double* Xij = Linv + 16 * ib * T + 16 * jb;
+    double* Xij = sx + 16 * ib * PLD + 16 * jb;
     if (jb < ib) {                             // t = sum_{k=j}^{i-1} L_ik X_kj
       d4 t = {0.0, 0.0, 0.0, 0.0};
-      for (int kb = jb; kb < ib; ++kb) mfma_ab(t, s + 16 * ib * PLD + 16 * kb, PLD, Linv + 16 * kb * T + 16 * jb, T, 16, 1.0);
-      blk_store(t, Xij, T);
+      for (int kb = jb; kb < ib; ++kb)
+        mfma_ab(t, s + 16 * ib * PLD + 16 * kb, PLD, sx + 16 * kb * PLD + 16 * jb, PLD, 16, 1.0);
+      blk_store(t, Xij, PLD);
     }
     __syncthreads();
     if (jb < ib) {                             // X_ij = -X_ii t
       d4 x = {0.0, 0.0, 0.0, 0.0};
-      mfma_ab(x, Linv + 16 * ib * T + 16 * ib, T, Xij, T, 16, -1.0);
-      blk_store(x, Xij, T);
+      mfma_ab(x, sx + 16 * ib * PLD + 16 * ib, PLD, Xij, PLD, 16, -1.0);
+      blk_store(x, Xij, PLD);
     }
     __syncthreads();
   }
+  for (int e = threadIdx.x; e < TT; e += NT) Linv[e] = sx[(e >> 6) * PLD + (e & 63)];
+  __syncthreads();
   return ok_all != 0;
 }
 
