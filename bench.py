@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -21,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PROFILE_SUMMARY = "clustered_n262144_loglik_grad_counters.txt"
 METRIC = "M-RA loglik+grad evals/s at n=2^18 (batched vs plain, 1 GPU); FP64 MFMA % peak"
 
 
@@ -60,6 +62,125 @@ def cpu_baseline(sample_n: int, sample_M: int, full_flops: float):
             "cpu": _cpu_name()}
 
 
+def _src_digest() -> str:
+    """sha256 over the library's HIP/C++ sources: ties a stored counter
+    summary to the kernels it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1507_04789_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing, names another kernel, or was taken
+    on other sources."""
+    path = os.path.join(ROOT, "profiles", PROFILE_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        m = re.match(r"^traffic\s+(\S+)\s+(\S+)\s+src\s+(\S+)", line.strip())
+        if m:
+            vals[m.group(1)] = (float(m.group(2)), m.group(3))
+    if kernel not in vals or vals[kernel][1] != _src_digest():
+        return None
+    return vals[kernel][0]
+
+
+def copy_probe(nbytes: int, reps: int = 3):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters (each launch reads and writes nbytes)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "reps": reps}))
+
+
+def _csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    m = re.match(r"^mra::(k_\w+)", name)
+    return m.group(1)[2:] if m else name[:40]
+
+
+def summarize_profiles(root: str, copy_bytes: int):
+    """Text summary of a profiling directory: root/trace (kernel trace +
+    stats of a bench run), root/fetch and root/write (FETCH_SIZE and
+    WRITE_SIZE of the same run), root/copy_fetch and root/copy_write (the
+    same counters on copy_probe).  Commands are read from root/commands.txt."""
+    out = []
+    cmds = os.path.join(root, "commands.txt")
+    if os.path.exists(cmds):
+        out.append("commands:")
+        out += ["  " + l.rstrip() for l in open(cmds) if l.strip()]
+    out.append("source digest: %s" % _src_digest())
+
+    def find(sub, suffix):
+        d = os.path.join(root, sub)
+        for dp, _, fs in os.walk(d):
+            for f in fs:
+                if f.endswith(suffix):
+                    return os.path.join(dp, f)
+        raise FileNotFoundError("%s/*%s" % (d, suffix))
+
+    stats = _csv(find("trace", "kernel_stats.csv"))
+    out.append("")
+    out.append("kernel stats (rocprofv3 --kernel-trace --stats):")
+    out.append("%-18s %6s %12s %12s %6s" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+    for r in stats[:20]:
+        out.append("%-18s %6s %12.3f %12.2f %6s" % (_short(r["Name"]), r["Calls"],
+                                                     float(r["TotalDurationNs"]) / 1e6,
+                                                     float(r["AverageNs"]) / 1e3, r["Percentage"]))
+
+    def counter(sub):
+        per = {}
+        for r in _csv(find(sub, "counter_collection.csv")):
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    def copy_factor(sub):
+        per = counter(sub)
+        # the largest dispatch is the probe's copy
+        vals = max((v for vs in per.values() for v in vs))
+        return copy_bytes / vals, vals
+
+    ff, fv = copy_factor("copy_fetch")
+    wf, wv = copy_factor("copy_write")
+    out.append("")
+    out.append("copy calibration: %d bytes read and written per copy; FETCH_SIZE %.1f, WRITE_SIZE %.1f "
+               "per dispatch -> %.2f and %.2f bytes per counter unit" % (copy_bytes, fv, wv, ff, wf))
+    fetch, write = counter("fetch"), counter("write")
+    out.append("")
+    out.append("HBM traffic per dispatch (counter x calibration), averaged over dispatches:")
+    out.append("%-18s %6s %12s %12s %12s" % ("kernel", "disp", "fetch_MB", "write_MB", "total_MB"))
+    rows = []
+    for k in fetch:
+        fb = ff * sum(fetch[k]) / len(fetch[k])
+        wb = wf * (sum(write.get(k, [0.0])) / max(len(write.get(k, [])), 1))
+        rows.append((_short(k), len(fetch[k]), fb, wb))
+    rows.sort(key=lambda x: -(x[2] + x[3]) * x[1])
+    for name, nd, fb, wb in rows:
+        out.append("%-18s %6d %12.2f %12.2f %12.2f" % (name, nd, fb / 1e6, wb / 1e6, (fb + wb) / 1e6))
+    out.append("")
+    out.append("machine-readable (kernel, HBM bytes per launch, source digest):")
+    for name, nd, fb, wb in rows:
+        out.append("traffic %s %.6g src %s" % (name, fb + wb, _src_digest()))
+    print("\n".join(out))
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -79,7 +200,18 @@ def main():
     ap.add_argument("--M", type=int, default=6)
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the one-launch-per-task form (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="print the text summary of a profiling directory and exit")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.copy_bytes)
+        return
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the M-RA path here runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -159,7 +291,8 @@ def main():
         "fp64_pct_peak_step": 100.0 * flops / (ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
         "algorithmic_flops_per_step": flops,
         "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": _stored_traffic(dom["name"]), "traffic_unit": "bytes",
                      "flops_per_launch": per_launch_flops, "avg_launch_ms": avg_ms},
         "kernels": [{"name": f["name"], "ms_per_step": f["total_ms"] / args.steps,
                      "tflops": (f["flops"] / (f["total_ms"] * 1e-3) / 1e12) if f["total_ms"] > 0 else None}
@@ -169,7 +302,7 @@ def main():
         "wall_s_timed": wall,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(16384, max(args.M - 2, 1), flops)
+        out["cpu_baseline"] = cpu_baseline(65536, max(args.M - 1, 1), flops)
     print(json.dumps(out))
 
 
