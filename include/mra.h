@@ -61,6 +61,15 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 #define MRA_PLAIN  2u   /* one kernel launch per region / task (comparison form) */
 #define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
 
+/* MRA_GRAPH: the first call with a given (call kind, n_theta, pointer
+ * arguments) captures its whole launch sequence, both internal streams
+ * included, on a private stream and keeps the instantiated graph; that call
+ * and every later call with the same key replays it with one hipGraphLaunch
+ * on the caller's stream.  Data behind the pointers (y, theta) is read at
+ * replay, so new values in the same buffers need no new capture.  At most
+ * 16 graphs are kept (the cache is emptied when a 17th key arrives);
+ * mra_bind empties it.  Calls made while profiling is enabled run eagerly. */
+
 typedef struct {
   int32_t d;            /* spatial dimension: 1 or 2 */
   int32_t M;            /* number of partition levels; M = 0 is the exact GP (Sec. 2.4) */

@@ -113,6 +113,10 @@ class Plan:
 
     def _prep(self, y, theta):
         torch = _torch()
+        for name, t in (("y", y), ("theta", theta)):
+            if isinstance(t, torch.Tensor) and t.dtype != torch.float64:
+                raise TypeError("%s is %s: the library computes in FP64 and takes float64 tensors "
+                                "(a narrower tensor has already lost precision)" % (name, t.dtype))
         y = torch.as_tensor(y, dtype=torch.float64)
         theta = torch.as_tensor(theta, dtype=torch.float64)
         if not y.is_cuda:
@@ -133,34 +137,45 @@ class Plan:
             raise MRAError(s, where, ": theta %d, level %d, region %d" % (th.value, lv.value, rg.value))
         _lib.check(s, where)
 
-    def loglik(self, y, theta):
-        """Log-likelihood for each row of theta (n_theta x 3)."""
+    def _out(self, t, shape):
         torch = _torch()
+        if t is None:
+            return torch.empty(shape, dtype=torch.float64, device=self.device)
+        if t.dtype != torch.float64 or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("output tensor must be contiguous float64 of shape %s on %s" % (shape, self.device))
+        return t
+
+    def loglik(self, y, theta, out=None):
+        """Log-likelihood for each row of theta (n_theta x 3); `out`
+        optionally names the output tensor (stable buffers let MRA_GRAPH
+        plans replay one captured graph)."""
         y, theta = self._prep(y, theta)
-        out = torch.empty(theta.shape[0], dtype=torch.float64, device=self.device)
+        out = self._out(out, (theta.shape[0],))
         s = _lib.lib().mra_loglik(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
                                   self._stream())
         self._fail(s, "mra_loglik")
         return out
 
-    def loglik_grad(self, y, theta):
-        """(loglik [n_theta], grad [n_theta, 3])."""
-        torch = _torch()
+    def loglik_grad(self, y, theta, out=None):
+        """(loglik [n_theta], grad [n_theta, 3]); out = (loglik, grad)
+        optionally names the output tensors."""
         y, theta = self._prep(y, theta)
-        out = torch.empty(theta.shape[0], dtype=torch.float64, device=self.device)
-        g = torch.empty(theta.shape[0], 3, dtype=torch.float64, device=self.device)
+        out, g = (None, None) if out is None else out
+        out = self._out(out, (theta.shape[0],))
+        g = self._out(g, (theta.shape[0], 3))
         s = _lib.lib().mra_loglik_grad(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
                                        g.data_ptr(), self._stream())
         self._fail(s, "mra_loglik_grad")
         return out, g
 
-    def predict(self, y, theta):
+    def predict(self, y, theta, out=None):
         """Posterior predictive (mean, var) of the latent process at the
-        plan's prediction locations, for one parameter vector."""
-        torch = _torch()
+        plan's prediction locations, for one parameter vector; out =
+        (mean, var) optionally names the output tensors."""
         y, theta = self._prep(y, theta)
-        mean = torch.empty(self.n_pred, dtype=torch.float64, device=self.device)
-        var = torch.empty(self.n_pred, dtype=torch.float64, device=self.device)
+        mean, var = (None, None) if out is None else out
+        mean = self._out(mean, (self.n_pred,))
+        var = self._out(var, (self.n_pred,))
         s = _lib.lib().mra_predict(self._h, y.data_ptr(), theta[:1].data_ptr(), mean.data_ptr(), var.data_ptr(),
                                    self._stream())
         self._fail(s, "mra_predict")

@@ -56,6 +56,70 @@ hipError_t ensure_side(mra_plan_s* H) {
   return hipSuccess;
 }
 
+}  // namespace
+
+// Captured launch sequences (MRA_GRAPH).  A call's whole launch sequence,
+// both streams included, is captured once on a private stream and replayed
+// with one hipGraphLaunch on the caller's stream.  Kernel arguments are baked
+// into the graph, so the key holds every pointer and count they depend on;
+// a bind (new arenas) drops the cache.  Nothing in the sequence is a memset
+// or copy node: buffers are cleared by kernels.
+struct GraphKey {
+  int kind;  // 0 loglik, 1 loglik + grad, 2 predict
+  int nth;
+  const void* p[5];
+  bool operator<(const GraphKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (nth != o.nth) return nth < o.nth;
+    for (int i = 0; i < 5; ++i)
+      if (p[i] != o.p[i]) return p[i] < o.p[i];
+    return false;
+  }
+};
+constexpr size_t kMaxGraphs = 16;
+struct GraphCache {
+  hipStream_t cap = nullptr;
+  std::map<GraphKey, hipGraphExec_t> exec;
+  void clear() {
+    for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
+    exec.clear();
+  }
+};
+
+namespace {
+
+// run `enqueue(stream)` on st directly, or through the plan's graph cache
+template <class F>
+hipError_t run_call(mra_plan_s* H, const GraphKey& key, hipStream_t st, F enqueue) {
+  const bool profiling = H->prof && H->prof->enabled;
+  if (!(H->cfg.flags & MRA_GRAPH) || profiling) return enqueue(st);
+  if (!H->graphs) {
+    H->graphs = new (std::nothrow) GraphCache();
+    if (!H->graphs) return hipErrorOutOfMemory;
+  }
+  GraphCache& C = *H->graphs;
+  auto it = C.exec.find(key);
+  if (it == C.exec.end()) {
+    hipError_t e;
+    if (C.exec.size() >= kMaxGraphs) C.clear();   // callers that keep changing buffers
+    if (!C.cap && (e = hipStreamCreateWithFlags(&C.cap, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(C.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t el = enqueue(C.cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(C.cap, &g);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return el != hipSuccess ? el : e;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    it = C.exec.emplace(key, x).first;
+  }
+  return hipGraphLaunch(it->second, st);
+}
+
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
                            hipStream_t st) {
   const bool overlap = !(H->cfg.flags & MRA_PLAIN);
@@ -191,6 +255,7 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   D.pleaf_n = (const int32_t*)(g + L.g_pleafn);
   D.pleaf_poff = (const int64_t*)(g + L.g_ppoff);
   D.work = (double*)d_work;
+  if (P->graphs) P->graphs->clear();
   P->d_geom = d_geom;
   P->d_work = d_work;
   P->bound = true;
@@ -204,16 +269,16 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   if (!d_y || !d_theta || !d_loglik) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
-  if (!(P->cfg.flags & MRA_PLAIN)) {
-    s = check_hip(ensure_side(P));
-    if (s != MRA_OK) return s;
-    s = check_hip(launch_forward_front(*P, d_y, d_theta, n_theta, st, (hipStream_t)P->side_stream, P->ev_fork,
-                                       P->ev_join));
-  } else {
-    s = check_hip(launch_forward_front(*P, d_y, d_theta, n_theta, st));
-  }
-  if (s != MRA_OK) return s;
-  s = check_hip(launch_forward_back(*P, n_theta, d_loglik, st));
+  const bool overlap = !(P->cfg.flags & MRA_PLAIN);
+  if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
+  const GraphKey key{0, n_theta, {d_y, d_theta, d_loglik, nullptr, nullptr}};
+  s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
+    hipError_t e = overlap ? launch_forward_front(*P, d_y, d_theta, n_theta, q, (hipStream_t)P->side_stream,
+                                                  P->ev_fork, P->ev_join)
+                           : launch_forward_front(*P, d_y, d_theta, n_theta, q);
+    if (e != hipSuccess) return e;
+    return launch_forward_back(*P, n_theta, d_loglik, q);
+  }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
   return MRA_OK;
@@ -226,7 +291,11 @@ mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_thet
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
-  s = check_hip(launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, st));
+  if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
+  const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, nullptr}};
+  s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
+    return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, q);
+  }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
   return MRA_OK;
@@ -240,9 +309,12 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
   if (P->n_pred == 0) return MRA_OK;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = 1;
-  s = check_hip(launch_forward(*P, d_y, d_theta, 1, nullptr, st));
-  if (s != MRA_OK) return s;
-  s = check_hip(launch_predict(*P, d_theta, d_mean, d_var, st));
+  const GraphKey key{2, 1, {d_y, d_theta, d_mean, d_var, nullptr}};
+  s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
+    hipError_t e = launch_forward(*P, d_y, d_theta, 1, nullptr, q);
+    if (e != hipSuccess) return e;
+    return launch_predict(*P, d_theta, d_mean, d_var, q);
+  }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
   return MRA_OK;
@@ -328,6 +400,11 @@ void mra_destroy(mra_plan_t P) {
   }
   if (P->ev_fork) (void)hipEventDestroy((hipEvent_t)P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy((hipEvent_t)P->ev_join);
+  if (P->graphs) {
+    P->graphs->clear();
+    if (P->graphs->cap) (void)hipStreamDestroy(P->graphs->cap);
+    delete P->graphs;
+  }
   delete P->prof;
   delete P;
 }

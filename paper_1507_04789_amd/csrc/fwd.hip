@@ -392,7 +392,7 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
   for (int m = 0; m < M; ++m) run("prior", m, F.prior[m], k_prior, P.nreg[m], theta, m);
-  run("leaf_rows", -1, F.leaf_rows, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
+  run.chunked("leaf_rows", -1, F.leaf_rows, nullptr, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
   run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
   const int64_t nfac = (int64_t)H.fac_tasks.size(), ntrsm = (int64_t)H.trsm_tasks.size() / 2;
   const int64_t nbig = (side && H.n_fac_big > 0) ? H.n_fac_big : 0;

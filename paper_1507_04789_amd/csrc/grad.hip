@@ -560,10 +560,10 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, d
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
-  run.grouped("rleaf_q", -1, F.rleaf_q, M + 1, k_rleaf_q, nrow * (M + 1));
+  run.chunked("rleaf_q", -1, F.rleaf_q, nullptr, k_rleaf_q, nrow * (M + 1));
   run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
   if (M > 0) {
-    run("rrows_leaf", -1, F.rrows + F.rleaf_wbar, k_rrows_leaf, nrow, theta);
+    run.chunked("rrows_leaf", -1, F.rrows + F.rleaf_wbar, H.cut_rrows, k_rrows_leaf, nrow, theta);
     run.grouped("rT_leaf", -1, F.rT_leaf, M * (M + 1) / 2, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
     for (int m = M - 1; m >= 0; --m) {
       run("rprior", m, F.rprior[m], k_rprior, P.nreg[m], theta, m);

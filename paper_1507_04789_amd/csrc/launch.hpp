@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -14,21 +15,31 @@ struct mra_plan_s;
 
 namespace mra {
 
-// Task index of a workgroup.  Batched launches of tasks that share inputs
-// (G consecutive task indices) place each group on one XCD: workgroups are
-// dispatched to the 8 XCDs round-robin by block index, so block b runs on
-// XCD b % 8; group g goes to XCD g % 8, and its G tasks take consecutive
-// slots there, so they find the group's inputs in that XCD's L2.  Blocks
-// past the last group return -1.
+// Task index of a workgroup.  Workgroups are dispatched to the 8 XCDs
+// round-robin by block index, so block b runs on XCD b % 8, and each XCD has
+// its own L2.  Batched launches of tasks that share inputs (G consecutive
+// task indices) place each group on one XCD: group g goes to XCD g % 8, and
+// its G tasks take consecutive slots there, so they find the group's inputs
+// in that XCD's L2.  G = 0 gives XCD x the contiguous chunk
+// [cut[x], cut[x+1]) of the task list, walked in order: tasks in tree order
+// that share ancestors run close together in time on one XCD.  The cuts
+// balance the chunks' estimated cost.  Blocks past the last task of their
+// group or chunk return -1.
 struct TaskMap {
-  int64_t t0;     // first task (plain form: the single task of the launch)
-  int64_t ntask;  // tasks in the launch (a multiple of G when G > 1)
-  int32_t G;      // group size; 1 = identity mapping
+  int64_t t0;       // first task (plain form: the single task of the launch)
+  int64_t ntask;    // tasks in the launch (a multiple of G when G > 1)
+  int32_t G;        // group size; 1 = identity mapping, 0 = one chunk per XCD
+  int32_t cut[9];   // G = 0: chunk boundaries, cut[0] = 0, cut[8] = ntask
 };
 
 __device__ __forceinline__ int64_t task_of(const TaskMap& m) {
   const int64_t b = blockIdx.x;
-  if (m.G <= 1) return m.t0 + b;
+  if (m.G == 1) return m.t0 + b;
+  if (m.G == 0) {
+    const int x = (int)(b & 7);
+    const int64_t t = m.cut[x] + (b >> 3);
+    return t < m.cut[x + 1] ? m.t0 + t : -1;
+  }
   const int64_t xcd = b & 7, s = b >> 3;
   const int64_t g = (s / m.G) * 8 + xcd;
   if (g * m.G >= m.ntask) return -1;
@@ -71,6 +82,17 @@ struct Runner {
   void operator()(const char* name, int level, double flops, K kern, int64_t ntask, A... args) const {
     grouped(name, level, flops, 1, kern, ntask, args...);
   }
+  // one contiguous chunk of the task list per XCD (G = 0), cut at `cut`
+  // (equal task counts when null)
+  template <class K, class... A>
+  void chunked(const char* name, int level, double flops, const int32_t* cut, K kern, int64_t ntask, A... args) const {
+    if (ntask <= 0) return;
+    TaskMap tm{0, ntask, 0, {}};
+    int64_t widest = 0;
+    for (int x = 0; x <= 8; ++x) tm.cut[x] = cut ? cut[x] : (int32_t)(ntask * x / 8);
+    for (int x = 0; x < 8; ++x) widest = std::max<int64_t>(widest, tm.cut[x + 1] - tm.cut[x]);
+    launch(name, level, flops, kern, ntask, dim3((unsigned)(8 * widest), nth), tm, args...);
+  }
   template <class K, class... A>
   void grouped(const char* name, int level, double flops, int G, K kern, int64_t ntask, A... args) const {
     range(name, level, flops, G, kern, 0, ntask, args...);
@@ -80,6 +102,19 @@ struct Runner {
   void range(const char* name, int level, double flops, int G, K kern, int64_t t_begin, int64_t t_end, A... args) const {
     const int64_t ntask = t_end - t_begin;
     if (ntask <= 0) return;
+    if (G == 1) {
+      launch(name, level, flops, kern, ntask, dim3((unsigned)ntask, nth), TaskMap{t_begin, ntask, 1, {}}, args...);
+    } else {
+      const int64_t ngroups = ntask / G;
+      const int64_t nblk = (ngroups + 7) / 8 * 8 * G;
+      launch(name, level, flops, kern, ntask, dim3((unsigned)nblk, nth), TaskMap{t_begin, ntask, G, {}}, args...);
+    }
+  }
+  // one batched launch of `grid` blocks with mapping tm, or in the plain form
+  // one launch per task
+  template <class K, class... A>
+  void launch(const char* name, int level, double flops, K kern, int64_t ntask, dim3 grid, const TaskMap& tm,
+              A... args) const {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof && prof->enabled) {
       e0 = prof->next();
@@ -87,14 +122,10 @@ struct Runner {
       if (e0) (void)hipEventRecord(e0, st);
     }
     if (plain) {
-      for (int64_t t = t_begin; t < t_end; ++t)
-        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., TaskMap{t, 1, 1});
-    } else if (G <= 1) {
-      hipLaunchKernelGGL(kern, dim3((unsigned)ntask, nth), dim3(256), 0, st, P, args..., TaskMap{t_begin, ntask, 1});
+      for (int64_t t = tm.t0; t < tm.t0 + ntask; ++t)
+        hipLaunchKernelGGL(kern, dim3(1, nth), dim3(256), 0, st, P, args..., TaskMap{t, 1, 1, {}});
     } else {
-      const int64_t ngroups = ntask / G;
-      const int64_t nblk = (ngroups + 7) / 8 * 8 * G;
-      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, nth), dim3(256), 0, st, P, args..., TaskMap{t_begin, ntask, G});
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, P, args..., tm);
     }
     if (e0 && e1) {
       (void)hipEventRecord(e1, st);

@@ -209,13 +209,35 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     if (nb == 0) continue;
     P->fac_tasks.push_back(i);
     if (nb >= 3) ++P->n_fac_big;
-    for (int64_t t = 0; t < nb; ++t) { P->row_tasks.push_back(i); P->row_tasks.push_back((int32_t)(P->leaf_poff[i] + t * T)); }
     for (int64_t bi = 0; bi < nb; ++bi)
       for (int64_t bj = 0; bj <= bi; ++bj) {
         P->sig_tasks.push_back(i); P->sig_tasks.push_back((int32_t)bi); P->sig_tasks.push_back((int32_t)bj);
       }
     for (int c = 0; c <= M; ++c) { P->trsm_tasks.push_back(i); P->trsm_tasks.push_back(c); }
     for (int64_t j = 0; j < nb; ++j) { P->linv_tasks.push_back(i); P->linv_tasks.push_back((int32_t)j); }
+  }
+  // row tiles in tree order (leaf index order is depth-first), so that
+  // consecutive tasks share ancestors
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    const int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
+    for (int64_t t = 0; t < nb; ++t) { P->row_tasks.push_back((int32_t)i); P->row_tasks.push_back((int32_t)(P->leaf_poff[i] + t * T)); }
+  }
+  {
+    // a reverse row sweep costs M(M+1)/2 + M ancestor block products plus M
+    // per tile of its leaf; cut the tree-ordered list into 8 runs of equal cost
+    const int64_t nrow = (int64_t)P->row_tasks.size() / 2;
+    std::vector<double> pre(nrow + 1, 0.0);
+    for (int64_t t = 0; t < nrow; ++t) {
+      const int32_t lf = P->row_tasks[2 * t];
+      const double nb = (double)((P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T);
+      pre[t + 1] = pre[t] + M * (M + 1) / 2 + M + M * nb;
+    }
+    for (int x = 0; x <= 8; ++x) {
+      const double goal = pre[nrow] * x / 8.0;
+      P->cut_rrows[x] = (int32_t)(std::lower_bound(pre.begin(), pre.end(), goal) - pre.begin());
+    }
+    P->cut_rrows[0] = 0;
+    P->cut_rrows[8] = (int32_t)nrow;
   }
   for (int64_t i = 0; i < n_leaves; ++i) {
     int64_t nb = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;

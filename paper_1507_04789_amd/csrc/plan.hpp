@@ -59,6 +59,7 @@ struct mra_plan_s {
   // task lists
   std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, linv_tasks, pred_tasks;
   int64_t n_fac_big = 0;   // leading fac_tasks (and M+1 trsm_tasks each) of leaves with >= 3 tiles
+  int32_t cut_rrows[9] = {};  // per-XCD chunks of row_tasks balancing the reverse row sweep's cost
   // layout
   mra::Layout lay;
   mra::DevPlan dp;

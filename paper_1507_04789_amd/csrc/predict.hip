@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
 hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st) {
   const DevPlan& P = H.dp;
   Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
-  run("predict", -1, H.pf.predict, k_predict, (int64_t)H.pred_tasks.size() / 2, theta, mean, var);
+  run.chunked("predict", -1, H.pf.predict, nullptr, k_predict, (int64_t)H.pred_tasks.size() / 2, theta, mean, var);
   return hipGetLastError();
 }
 

@@ -89,3 +89,13 @@ def test_flop_model_counts():
     p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov)
     assert p.info["n_leaves"] == 64 and p.info["n_regions"] == 85
     assert p.info["flops_grad"] > p.info["flops_loglik"] > 0
+
+
+def test_binding_rejects_narrow_tensors():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(3)
+    p = Plan(g.random((200, 2)), M=1, J=4, r=4, cov="exponential")
+    with pytest.raises(TypeError):
+        p.loglik(torch.zeros(200, dtype=torch.float32), np.zeros(3))
+    with pytest.raises(TypeError):
+        p.loglik_grad(np.zeros(200), torch.zeros(1, 3, dtype=torch.float32))

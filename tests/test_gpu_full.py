@@ -43,7 +43,7 @@ def test_full_size_bench_configuration(data):
     p.bind("cuda:0")
     z = torch.tensor(w.z, device="cuda:0")
     for pt in gold["points"]:
-        th = torch.tensor(pt["theta"], device="cuda:0").reshape(1, 3)
+        th = torch.tensor(pt["theta"], dtype=torch.float64, device="cuda:0").reshape(1, 3)
         ll, g = p.loglik_grad(z, th)
         ll1 = p.loglik(z, th)
         torch.cuda.synchronize()
@@ -60,7 +60,7 @@ def test_full_size_theta_batch(data):
     p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=k)
     p.bind("cuda:0")
     z = torch.tensor(w.z, device="cuda:0")
-    th = torch.tensor([pt["theta"] for pt in gold["points"]], device="cuda:0")
+    th = torch.tensor([pt["theta"] for pt in gold["points"]], dtype=torch.float64, device="cuda:0")
     ll, g = p.loglik_grad(z, th)
     ll, g = ll.cpu().numpy(), g.cpu().numpy()
     for i, pt in enumerate(gold["points"]):
