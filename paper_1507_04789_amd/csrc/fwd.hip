@@ -228,21 +228,27 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
   }, lds);
   acc_store(acc, po.A(k, l), T);
   if (k == l) {      // w^k = sum_c Y^k_c' y_c: column threadIdx & 63, rows split over the waves
-    double w = 0.0;
     const int col = threadIdx.x & 63;
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = 0; c < P.J; ++c) {
       const int64_t leaf = pidx * P.J + c;
-      for (int64_t p = P.leaf_poff[leaf] + wave_id(); p < P.leaf_poff[leaf + 1]; p += 4)
-        w += Yk[p * T + col] * Yz[p * T];
+      const int64_t end = P.leaf_poff[leaf] + P.leaf_n[leaf];
+      int64_t p = P.leaf_poff[leaf] + wave_id();
+      for (; p + 12 < end; p += 16) {   // four rows in flight
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] += Yk[(p + 4 * q) * T + col] * Yz[(p + 4 * q) * T];
+      }
+      for (; p < end; p += 4) w[0] += Yk[p * T + col] * Yz[p * T];
     }
-    w = wave_col_sum(w, lds);
-    if (threadIdx.x < T) po.omega(k)[threadIdx.x] = w;
+    const double ws = wave_col_sum((w[0] + w[1]) + (w[2] + w[3]), lds);
+    if (threadIdx.x < T) po.omega(k)[threadIdx.x] = ws;
   }
   if (kl == 0) {
     double u = 0.0;
     for (int c = 0; c < P.J; ++c) {
       const int64_t leaf = pidx * P.J + c;
-      for (int64_t p = P.leaf_poff[leaf] + threadIdx.x; p < P.leaf_poff[leaf + 1]; p += NT) u += Yz[p * T] * Yz[p * T];
+      for (int64_t p = P.leaf_poff[leaf] + threadIdx.x; p < P.leaf_poff[leaf] + P.leaf_n[leaf]; p += NT)
+        u += Yz[p * T] * Yz[p * T];
     }
     u = block_sum(u, red);
     if (threadIdx.x == 0) {
