@@ -60,6 +60,8 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 #define MRA_SYNC   1u   /* synchronise after each call and check factor status */
 #define MRA_PLAIN  2u   /* one kernel launch per region / task (comparison form) */
 #define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
+#define MRA_NO_GRAD 8u  /* mra_loglik and mra_predict only: the work arena leaves out the reverse
+                           pass's buffers, and mra_loglik_grad returns MRA_ESTATE */
 
 /* MRA_GRAPH: the first call with a given (call kind, n_theta, pointer
  * arguments) captures its whole launch sequence, both internal streams
@@ -78,7 +80,7 @@ typedef struct {
   double lo[2], hi[2];  /* domain box (only the first d entries are read) */
   int32_t cov;          /* mra_cov */
   int32_t max_theta;    /* largest parameter batch a call may pass (>= 1) */
-  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH */
+  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD */
 } mra_config;
 
 typedef struct {

@@ -13,9 +13,9 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import MRA_GRAPH, MRA_PLAIN, MRA_SYNC, MRAError
+from ._lib import MRA_GRAPH, MRA_NO_GRAD, MRA_PLAIN, MRA_SYNC, MRAError
 
-__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH"]
+__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH", "MRA_NO_GRAD"]
 
 _COV = {"exponential": _lib.MRA_COV_EXPONENTIAL, "matern32": _lib.MRA_COV_MATERN32}
 

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libmra.so")
 
 MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EHIP, MRA_ESTATE = 0, -1, -2, -3, -4, -5
 MRA_COV_EXPONENTIAL, MRA_COV_MATERN32 = 0, 1
-MRA_SYNC, MRA_PLAIN, MRA_GRAPH = 1, 2, 4
+MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD = 1, 2, 4, 8
 
 # every symbol the header declares
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",

@@ -289,6 +289,7 @@ mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_thet
   mra_status s = check_call(P, n_theta);
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
+  if (P->cfg.flags & MRA_NO_GRAD) return MRA_ESTATE;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
   if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;

@@ -86,6 +86,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   if (!cfg || (!h_locs && n > 0) || n < 1 || n_pred < 0 || (n_pred > 0 && !h_pred)) return MRA_EINVAL;
   const int d = cfg->d, M = cfg->M, J = cfg->J, r = cfg->r;
   if (d < 1 || d > 2 || M < 0 || M >= MAXL || r < 1 || r > T || cfg->max_theta < 1) return MRA_EINVAL;
+  if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD)) return MRA_EINVAL;
   if (d == 2 && J != 1 && J != 4) return MRA_EINVAL;
   if (d == 1 && (J < 1 || J > 8)) return MRA_EINVAL;
   if (cfg->cov != MRA_COV_EXPONENTIAL && cfg->cov != MRA_COV_MATERN32) return MRA_EINVAL;
@@ -297,19 +298,26 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   }
   // reverse pass: per internal region G row tiles (m+1), omega-bar (T),
   // T-sums ((m+1)(m+2)/2 tiles), W-bar rows (m tiles) and W-bar^m (1 tile)
-  for (int m = 0; m < M; ++m) {
-    int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
-    D.grad_stride[m] = round_up((m + 1) * TT + T + nA * TT + m * TT + TT, 32);
-    D.grad_off[m] = wtake(P->nreg[m] * D.grad_stride[m]);
+  if (!(cfg->flags & MRA_NO_GRAD)) {
+    for (int m = 0; m < M; ++m) {
+      int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
+      D.grad_stride[m] = round_up((m + 1) * TT + T + nA * TT + m * TT + TT, 32);
+      D.grad_off[m] = wtake(P->nreg[m] * D.grad_stride[m]);
+    }
+    D.off_v = wtake((M + 1) * D.plane);
+    D.off_linv = wtake(P->n_sig_tiles * TT);
+    // buffers that are dead by the time the reverse pass writes them: Y
+    // (last read by the leaf products and by V = L^-T Y, both finished before
+    // Q = V Fbar is formed) holds Q, and each W-bar row tile overwrites the Q
+    // tile of the same rows and plane after reading it; Sigma-bar takes the
+    // tiles of the leaf factor, whose last readers (V and L^-1) have finished
+    D.off_q = D.off_y;
+    D.off_wbar = D.off_y;
+    D.off_sbar = D.off_sig;
+    // gradient partial sums: one slot per task of every gradient-producing launch
+    D.n_gpart = (int64_t)P->sig_tasks.size() / 3 + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
+    D.off_gpart = wtake(D.n_gpart * 4);
   }
-  D.off_v = wtake((M + 1) * D.plane);
-  D.off_q = wtake((M + 1) * D.plane);
-  D.off_sbar = wtake(P->n_sig_tiles * TT);
-  D.off_linv = wtake(P->n_sig_tiles * TT);
-  D.off_wbar = wtake(std::max(M, 1) * D.plane);
-  // gradient partial sums: one slot per task of every gradient-producing launch
-  D.n_gpart = (int64_t)P->sig_tasks.size() / 3 + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
-  D.off_gpart = wtake(D.n_gpart * 4);
   D.off_pw = wtake(std::max(M, 1) * P->ppad * T);
   int64_t nbmax = 1;
   for (int64_t i = 0; i < n_leaves; ++i)

@@ -99,3 +99,9 @@ def test_binding_rejects_narrow_tensors():
         p.loglik(torch.zeros(200, dtype=torch.float32), np.zeros(3))
     with pytest.raises(TypeError):
         p.loglik_grad(np.zeros(200), torch.zeros(1, 3, dtype=torch.float32))
+
+
+def test_rejects_unknown_flags():
+    g = np.random.default_rng(4)
+    with pytest.raises(MRAError):
+        Plan(g.random((100, 2)), M=1, J=4, r=4, cov="exponential", flags=64)

@@ -129,3 +129,22 @@ def test_failure_reports_theta():
     assert math.isnan(out[1]) and np.isfinite(out[[0, 2]]).all()
     ref = _oracle(locs, z, "matern32", ths[2], 2, 4, 16)
     assert abs(out[2] - ref) <= RTOL * abs(ref)
+
+
+def test_no_grad_plan_matches_and_refuses_gradient():
+    from paper_1507_04789_amd import MRA_NO_GRAD
+    w = wl.clustered(n=32768, M=4, r=64)
+    print("case: clustered n=%d M=%d, loglik-only plan" % (len(w.z), w.M), flush=True)
+    full = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=2)
+    lean = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=2, flags=MRA_SYNC | MRA_NO_GRAD)
+    assert lean.work_bytes < full.work_bytes
+    z = w.z
+    ths = wl.theta_draws(2, 9)
+    a = full.loglik(z, ths).cpu().numpy()
+    b = lean.loglik(z, ths).cpu().numpy()
+    assert np.array_equal(a, b)
+    # the gradient call on the full plan leaves the loglik-only results unchanged
+    ll, _ = full.loglik_grad(z, ths[:1])
+    assert float(ll[0]) == a[0]
+    with pytest.raises(MRAError):
+        lean.loglik_grad(z, ths[:1])
