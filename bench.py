@@ -181,6 +181,78 @@ def summarize_profiles(root: str, copy_bytes: int):
     print("\n".join(out))
 
 
+def _time_calls(fn, steps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def secondary_configs(dev, w2, theta_batch):
+    """The other measured workloads, each on captured-graph replays:
+    the small uniform case (n = 4096, exponential, M = 3, r = 16, 1000
+    prediction points; latency of one loglik+grad and one kriging call),
+    the clustered n = 2^18 log-likelihood alone, and 64 parameter vectors on
+    the clustered data (log kappa ~ U[log 0.02, log 0.3], log sigma^2 ~
+    U[-1, 1], log tau^2 ~ U[-6, -2], seed 41) in batches of theta_batch
+    vectors per call (one launch per level for the whole batch)."""
+    import torch
+    from paper_1507_04789_amd import MRA_GRAPH, MRA_NO_GRAD, Plan
+    from paper_1507_04789_amd import workloads as wl
+    res = {}
+    w1 = wl.small_uniform()
+    p1 = Plan(w1.locs, M=w1.M, J=w1.J, r=w1.r, cov=w1.cov, pred=w1.pred, flags=MRA_GRAPH)
+    p1.bind(dev)
+    z1 = torch.tensor(w1.z, device=dev)
+    t1 = torch.tensor(w1.theta, device=dev).reshape(1, 3)
+    o1 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, 3, dtype=torch.float64, device=dev))
+    pr = (torch.empty(w1.pred.shape[0], dtype=torch.float64, device=dev),
+          torch.empty(w1.pred.shape[0], dtype=torch.float64, device=dev))
+    ms_g = _time_calls(lambda: p1.loglik_grad(z1, t1, out=o1), 50)
+    ms_p = _time_calls(lambda: p1.predict(z1, t1, out=pr), 50)
+    res["uniform_n4096_exp_M3_r16"] = {"loglik_grad_ms": ms_g, "predict_ms": ms_p, "n_pred": int(w1.pred.shape[0]),
+                                       "flops_grad": p1.info["flops_grad"], "flops_predict": p1.info["flops_predict"]}
+    del p1
+    z2 = torch.tensor(w2.z, device=dev)
+    p2 = Plan(w2.locs, M=w2.M, J=w2.J, r=w2.r, cov=w2.cov, flags=MRA_GRAPH | MRA_NO_GRAD)
+    p2.bind(dev)
+    t2 = torch.tensor(w2.theta, device=dev).reshape(1, 3)
+    o2 = torch.empty(1, dtype=torch.float64, device=dev)
+    ms_l = _time_calls(lambda: p2.loglik(z2, t2, out=o2), 10)
+    res["clustered_n262144_loglik"] = {"ms": ms_l, "evals_per_s": 1000.0 / ms_l,
+                                       "fp64_pct_peak": 100.0 * p2.info["flops_loglik"] / (ms_l * 1e-3) /
+                                       (PEAK_FP64_TFLOPS * 1e12)}
+    del p2
+    torch.cuda.empty_cache()
+    ths = torch.tensor(wl.theta_draws(64, 41), device=dev)
+    B = max(1, min(theta_batch, 64))
+    p4 = Plan(w2.locs, M=w2.M, J=w2.J, r=w2.r, cov=w2.cov, max_theta=B, flags=MRA_GRAPH)
+    p4.bind(dev)
+    chunks = [ths[i:i + B].contiguous() for i in range(0, 64, B)]
+    outs = [(torch.empty(c.shape[0], dtype=torch.float64, device=dev),
+             torch.empty(c.shape[0], 3, dtype=torch.float64, device=dev)) for c in chunks]
+
+    def all64():
+        for c, o in zip(chunks, outs):
+            p4.loglik_grad(z2, c, out=o)
+    ms4 = _time_calls(all64, 2, warmup=1)
+    lls = torch.cat([o[0] for o in outs])
+    res["clustered_n262144_64theta_loglik_grad"] = {
+        "ms_for_64": ms4, "evals_per_s": 64 * 1000.0 / ms4, "theta_per_call": B,
+        "fp64_pct_peak": 100.0 * 64 * p4.info["flops_grad"] / (ms4 * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
+        "finite": bool(torch.isfinite(lls).all())}
+    del p4
+    torch.cuda.empty_cache()
+    return res
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -201,6 +273,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the one-launch-per-task form (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of captured-graph replays")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary workloads (small uniform case, loglik only, 64-vector batch)")
+    ap.add_argument("--theta-batch", type=int, default=16, help="parameter vectors per call in the 64-vector case")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -286,6 +361,12 @@ def main():
         del pplan
         torch.cuda.empty_cache()
 
+    secondary = None
+    if not args.no_secondary:
+        del plan
+        torch.cuda.empty_cache()
+        secondary = secondary_configs(dev, w, args.theta_batch)
+
     out = {
         "metric": METRIC,
         "value": 1000.0 / ms,
@@ -316,6 +397,7 @@ def main():
                           "note": "eager launches with HIP events around every launch group; source of the "
                                   "kernel table and the roofline"},
         "plain": plain,
+        "secondary": secondary,
         "result": {"loglik": llv, "grad": gv},
         "wall_s_timed": wall,
     }
