@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of captured-graph replays")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workloads (small uniform case, loglik only, 64-vector batch)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes (no autotuning)")
     ap.add_argument("--theta-batch", type=int, default=16, help="parameter vectors per call in the 64-vector case")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
@@ -325,6 +326,11 @@ def main():
             plan.profile(False)
         return e0.elapsed_time(e1) / steps, wall, stats
 
+    tuning = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuning = plan.autotune(z, th, reps=2)
+        tuning["tuning_s"] = time.perf_counter() - t0
     for _ in range(args.warmup):
         plan.loglik_grad(z, th, out=(ll, g))
     torch.cuda.synchronize()
@@ -393,6 +399,7 @@ def main():
                      "tflops": (f["flops"] / (f["total_ms"] * 1e-3) / 1e12) if f["total_ms"] > 0 else None}
                     for f in fam],
         "form": "eager" if args.eager else "hipgraph",
+        "tuning": tuning,
         "profiled_pass": {"steps": prof_steps, "ms_per_step": ms_prof,
                           "note": "eager launches with HIP events around every launch group; source of the "
                                   "kernel table and the roofline"},

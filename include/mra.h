@@ -167,6 +167,36 @@ mra_status mra_predict(mra_plan_t plan, const double* d_y, const double* d_theta
 mra_status mra_last_failure(mra_plan_t plan, int32_t* theta_idx, int32_t* level,
                             int64_t* region, void* stream);
 
+/*
+ * Autotuner.  Every batched launch belongs to a kernel family (prior,
+ * leaf_rows, leaf_sigma, leaf_potrf, leaf_trsm, leaf_reduce, post,
+ * post_reduce, rleaf_v, rleaf_linv, rpost, rleaf_q, rleaf_sbar, rrows_leaf,
+ * rT_leaf, rprior, rT, predict).  A family's launch shape is the mapping of
+ * workgroups to its tasks: "identity", "grouped" (related tasks, e.g. the
+ * planes of one leaf, on one XCD and L2) or "chunked" (one contiguous run of
+ * the tree-ordered task list per XCD); "default" keeps the built-in choice.
+ * big_leaf_tiles is the tile count from which a leaf is factored on the
+ * second stream (0: none).  Shapes only permute work: results are the same
+ * bit for bit under every table.
+ *
+ * mra_autotune times mra_loglik_grad (mra_loglik for MRA_NO_GRAD plans) on
+ * the given device data, `reps` calls per candidate after one warm-up call,
+ * over one pass of coordinate descent (each family's shapes, then the leaf
+ * cut), keeps the fastest table, and writes it as JSON to out_json (cap
+ * bytes; *len receives the length, without the terminating zero; MRA_ENOMEM
+ * if cap is too small, the table is applied anyway).  d_loglik [n_theta] and
+ * d_grad [n_theta][3] are scratch outputs.  Synchronises `stream`.
+ * mra_get_tuning writes the current table; mra_set_tuning applies a table
+ * produced by either (unknown keys are ignored, unknown shapes give
+ * MRA_EINVAL).  Both drop captured graphs.  Host only apart from
+ * mra_autotune.
+ */
+mra_status mra_autotune(mra_plan_t plan, const double* d_y, const double* d_theta, int32_t n_theta,
+                        double* d_loglik, double* d_grad, int32_t reps, char* out_json, size_t cap,
+                        size_t* len, void* stream);
+mra_status mra_get_tuning(mra_plan_t plan, char* out_json, size_t cap, size_t* len);
+mra_status mra_set_tuning(mra_plan_t plan, const char* json);
+
 /* Per-kernel timing (tracing).  mra_profile(plan, 1) enables HIP-event
  * timing of every launch group of the following calls on their streams and
  * clears earlier records; mra_profile(plan, 0) disables it.

@@ -181,6 +181,36 @@ class Plan:
         self._fail(s, "mra_predict")
         return mean, var
 
+    # -- autotuning -------------------------------------------------------------
+    def autotune(self, y, theta, reps: int = 3):
+        """Time the launch shapes of every kernel family on this data and keep
+        the fastest (results do not depend on the shapes); returns the table."""
+        import json
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        ll = torch.empty(theta.shape[0], dtype=torch.float64, device=self.device)
+        g = torch.empty(theta.shape[0], 3, dtype=torch.float64, device=self.device)
+        buf = C.create_string_buffer(8192)
+        n = C.c_size_t()
+        s = _lib.lib().mra_autotune(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], ll.data_ptr(),
+                                    g.data_ptr(), reps, buf, len(buf), C.byref(n), self._stream())
+        self._fail(s, "mra_autotune")
+        return json.loads(buf.value.decode())
+
+    def tuning(self):
+        """The current tuning table."""
+        import json
+        buf = C.create_string_buffer(8192)
+        n = C.c_size_t()
+        _lib.check(_lib.lib().mra_get_tuning(self._h, buf, len(buf), C.byref(n)), "mra_get_tuning")
+        return json.loads(buf.value.decode())
+
+    def set_tuning(self, table):
+        """Apply a table from autotune() / tuning() (dict or JSON text)."""
+        import json
+        text = table if isinstance(table, str) else json.dumps(table)
+        _lib.check(_lib.lib().mra_set_tuning(self._h, text.encode()), "mra_set_tuning")
+
     # -- tracing ----------------------------------------------------------------
     def profile(self, enable: bool = True):
         """Enable (and clear) or disable per-kernel HIP-event timing."""

@@ -14,7 +14,7 @@ MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD = 1, 2, 4, 8
 # every symbol the header declares
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",
            "mra_loglik_grad", "mra_predict", "mra_last_failure", "mra_profile", "mra_profile_read",
-           "mra_status_string", "mra_destroy"]
+           "mra_status_string", "mra_destroy", "mra_autotune", "mra_get_tuning", "mra_set_tuning"]
 
 
 class Config(C.Structure):
@@ -65,6 +65,9 @@ def lib() -> C.CDLL:
     L.mra_profile_read.argtypes = [vp, C.POINTER(PhaseStat), i32, C.POINTER(i32), vp]
     L.mra_status_string.argtypes = [i32]
     L.mra_status_string.restype = C.c_char_p
+    L.mra_autotune.argtypes = [vp, vp, vp, i32, vp, vp, i32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t), vp]
+    L.mra_get_tuning.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.mra_set_tuning.argtypes = [vp, C.c_char_p]
     L.mra_destroy.argtypes = [vp]
     L.mra_destroy.restype = None
     for name in SYMBOLS:

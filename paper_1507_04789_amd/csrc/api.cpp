@@ -1,8 +1,11 @@
 // C ABI of the M-RA library (declared in include/mra.h).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <new>
 #include <utility>
 
@@ -141,6 +144,52 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
   if (overlap && (e = hipStreamWaitEvent(st, (hipEvent_t)H->ev_join, 0)) != hipSuccess) return e;
   return launch_grad_rest(*H, theta, nth, g, st);
+}
+
+// ---- tuning table (JSON) ----
+std::string tuning_json(const mra_plan_s* H, double ms) {
+  std::string j = "{\"version\": 1, ";
+  char buf[96];
+  if (ms > 0) {
+    std::snprintf(buf, sizeof buf, "\"ms_per_call\": %.6g, ", ms);
+    j += buf;
+  }
+  std::snprintf(buf, sizeof buf, "\"big_leaf_tiles\": %d, \"families\": {", H->big_tiles);
+  j += buf;
+  for (int f = 0; f < F_COUNT; ++f) {
+    std::snprintf(buf, sizeof buf, "%s\"%s\": \"%s\"", f ? ", " : "", fam_name(f), map_name(H->tune[f]));
+    j += buf;
+  }
+  j += "}}";
+  return j;
+}
+
+mra_status copy_out(const std::string& j, char* out, size_t cap, size_t* len) {
+  if (len) *len = j.size();
+  if (!out) return MRA_OK;
+  if (cap < j.size() + 1) return MRA_ENOMEM;
+  std::memcpy(out, j.c_str(), j.size() + 1);
+  return MRA_OK;
+}
+
+// value of "key": in a flat JSON text: a quoted string or a number
+bool json_value(const char* js, const char* key, std::string& val) {
+  const std::string k = std::string("\"") + key + "\"";
+  const char* p = std::strstr(js, k.c_str());
+  if (!p) return false;
+  p += k.size();
+  while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+  if (*p != ':') return false;
+  ++p;
+  while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+  val.clear();
+  if (*p == '"') {
+    ++p;
+    while (*p && *p != '"') val += *p++;
+    return *p == '"';
+  }
+  while (*p && (*p == '-' || (*p >= '0' && *p <= '9'))) val += *p++;
+  return !val.empty();
 }
 
 mra_status check_call(const mra_plan_s* H, int nth) {
@@ -331,6 +380,118 @@ mra_status mra_last_failure(mra_plan_t P, int32_t* theta_idx, int32_t* level, in
   if (level) *level = P->fail_level;
   if (region) *region = P->fail_region;
   return MRA_OK;
+}
+
+mra_status mra_get_tuning(mra_plan_t P, char* out_json, size_t cap, size_t* len) {
+  if (!P) return MRA_EINVAL;
+  return copy_out(tuning_json(P, 0.0), out_json, cap, len);
+}
+
+mra_status mra_set_tuning(mra_plan_t P, const char* json) {
+  if (!P || !json) return MRA_EINVAL;
+  uint8_t t[32] = {};
+  int32_t big = P->big_tiles;
+  std::string v;
+  for (int f = 0; f < F_COUNT; ++f) {
+    if (!json_value(json, fam_name(f), v)) continue;
+    int m = -1;
+    for (int c = 0; c < 4; ++c)
+      if (v == map_name(c)) m = c;
+    if (m < 0) return MRA_EINVAL;
+    t[f] = (uint8_t)m;
+  }
+  if (json_value(json, "big_leaf_tiles", v)) {
+    big = std::atoi(v.c_str());
+    if (big < 0 || big > 64) return MRA_EINVAL;
+  }
+  std::memcpy(P->tune, t, sizeof t);
+  P->big_tiles = big;
+  if (P->graphs) P->graphs->clear();
+  return MRA_OK;
+}
+
+mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
+                        double* d_grad, int32_t reps, char* out_json, size_t cap, size_t* len, void* stream) {
+  mra_status s = check_call(P, n_theta);
+  if (s != MRA_OK) return s;
+  const bool grad = !(P->cfg.flags & MRA_NO_GRAD);
+  if (!d_y || !d_theta || !d_loglik || (grad && !d_grad) || reps < 1) return MRA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const bool overlap = !(P->cfg.flags & MRA_PLAIN);
+  if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
+  const bool prof = P->prof && P->prof->enabled;
+  if (prof) P->prof->enabled = false;
+  P->last_nth = n_theta;
+  auto call = [&]() -> hipError_t {
+    if (grad) return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, st);
+    hipError_t e = overlap ? launch_forward_front(*P, d_y, d_theta, n_theta, st, (hipStream_t)P->side_stream,
+                                                  P->ev_fork, P->ev_join)
+                           : launch_forward_front(*P, d_y, d_theta, n_theta, st);
+    return e != hipSuccess ? e : launch_forward_back(*P, n_theta, d_loglik, st);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (prof) P->prof->enabled = true;
+    return MRA_EHIP;
+  }
+  bool ok = true;
+  auto measure = [&]() -> double {
+    if (call() != hipSuccess) ok = false;   // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r)
+      if (call() != hipSuccess) ok = false;
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ok = false;
+    return ok ? (double)ms / reps : 1e30;
+  };
+  // coordinate descent: one pass over the families, then the large-leaf cut;
+  // a change is kept only if it is faster by more than 0.5 %
+  const bool grouped[F_COUNT] = {false, false, false, false, true, true, false, true, true, false,
+                                 false, true, false, false, true, false, true, false};
+  const bool reverse[F_COUNT] = {false, false, false, false, false, false, false, false, true, true,
+                                 true, true, true, true, true, true, true, false};
+  double best = measure();
+  for (int f = 0; f < F_COUNT && ok; ++f) {
+    if (f == F_PREDICT || (reverse[f] && !grad)) continue;
+    const uint8_t keep = P->tune[f];
+    uint8_t pick = keep;
+    for (uint8_t m = MAP_IDENTITY; m <= MAP_CHUNKED && ok; ++m) {
+      if (m == MAP_GROUPED && !grouped[f]) continue;
+      P->tune[f] = m;
+      const double t = measure();
+      if (t < best * 0.995) {
+        best = t;
+        pick = m;
+      }
+    }
+    P->tune[f] = pick;
+  }
+  if (overlap && ok) {
+    const int32_t keep = P->big_tiles;
+    int32_t pick = keep;
+    for (int32_t b : {0, 2, 3, 4, 6}) {
+      if (b == keep) continue;
+      P->big_tiles = b;
+      const double t = measure();
+      if (t < best * 0.995) {
+        best = t;
+        pick = b;
+      }
+    }
+    P->big_tiles = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (prof) P->prof->enabled = true;
+  if (P->graphs) P->graphs->clear();
+  if (!ok) return MRA_EHIP;
+  if (P->cfg.flags & MRA_SYNC) {
+    s = collect_failures(P, n_theta, st);
+    if (s != MRA_OK) return s;
+  }
+  return copy_out(tuning_json(P, best), out_json, cap, len);
 }
 
 mra_status mra_profile(mra_plan_t P, int32_t enable) {

@@ -392,27 +392,33 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   int64_t gx = (P.plane + NT - 1) / NT;
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
-  for (int m = 0; m < M; ++m) run("prior", m, F.prior[m], k_prior, P.nreg[m], theta, m);
-  run.chunked("leaf_rows", -1, F.leaf_rows, nullptr, k_leaf_rows, (int64_t)H.row_tasks.size() / 2, theta);
-  run("leaf_sigma", -1, F.sigma, k_sigma, (int64_t)H.sig_tasks.size() / 3, theta);
+  for (int m = 0; m < M; ++m)
+    run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, P.nreg[m], theta, m);
+  run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,
+            (int64_t)H.row_tasks.size() / 2, theta);
+  run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, F.sigma, 1, nullptr, k_sigma, 0, (int64_t)H.sig_tasks.size() / 3,
+            theta);
   const int64_t nfac = (int64_t)H.fac_tasks.size(), ntrsm = (int64_t)H.trsm_tasks.size() / 2;
-  const int64_t nbig = (side && H.n_fac_big > 0) ? H.n_fac_big : 0;
+  const int64_t nbig = side ? H.nbig() : 0;
   if (nbig > 0) {
     hipError_t e;
     if ((e = hipEventRecord((hipEvent_t)ev_fork, st)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(side, (hipEvent_t)ev_fork, 0)) != hipSuccess) return e;
-    Runner rs{P, nth, side, false, H.prof};
-    rs.range("leaf_potrf_big", -1, F.potrf_big, 1, k_leaf_potrf, 0, nbig);
-    rs.range("leaf_trsm_big", -1, F.trsm_big, M + 1, k_leaf_trsm, 0, nbig * (M + 1));
+    Runner rs{P, nth, side, false, H.prof, H.tune};
+    const double fpb = H.potrf_flops_big(nbig), ftb = H.trsm_flops_big(nbig);
+    rs.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf_big", -1, fpb, 1, nullptr, k_leaf_potrf, 0, nbig);
+    rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm, 0, nbig * (M + 1));
     if ((e = hipEventRecord((hipEvent_t)ev_join, side)) != hipSuccess) return e;
   }
-  run.range("leaf_potrf", -1, F.potrf - (nbig ? F.potrf_big : 0.0), 1, k_leaf_potrf, nbig, nfac);
-  run.range("leaf_trsm", -1, F.trsm - (nbig ? F.trsm_big : 0.0), M + 1, k_leaf_trsm, nbig * (M + 1), ntrsm);
+  run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, F.potrf - H.potrf_flops_big(nbig), 1, nullptr, k_leaf_potrf, nbig,
+            nfac);
+  run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm,
+            nbig * (M + 1), ntrsm);
   if (nbig > 0) {
     hipError_t e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
     if (e != hipSuccess) return e;
@@ -425,16 +431,18 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   if (M == 0) {
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
-    run.grouped("leaf_reduce", -1, F.leaf_reduce, M * (M + 1) / 2, k_leaf_reduce, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    const int nkl = M * (M + 1) / 2;
+    run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, F.leaf_reduce, nkl, nullptr, k_leaf_reduce, 0,
+              P.nreg[M - 1] * (int64_t)nkl);
     for (int m = M - 1; m >= 0; --m) {
-      run("post", m, F.post[m], k_post, P.nreg[m], m, out_loglik);
+      run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, P.nreg[m], m, out_loglik);
       if (m > 0)
-        run.grouped("post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, k_post_reduce,
-                    P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+        run.tuned(F_POST_REDUCE, MAP_GROUPED, "post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, nullptr,
+                  k_post_reduce, 0, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);

@@ -533,9 +533,11 @@ hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
-  run.grouped("rleaf_v", -1, F.rleaf_v, M + 1, k_rleaf_v, (int64_t)H.trsm_tasks.size() / 2);
-  run("rleaf_linv", -1, F.rleaf_linv, k_rleaf_linv, (int64_t)H.linv_tasks.size() / 2);
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  run.tuned(F_RLEAF_V, MAP_GROUPED, "rleaf_v", -1, F.rleaf_v, M + 1, nullptr, k_rleaf_v, 0,
+            (int64_t)H.trsm_tasks.size() / 2);
+  run.tuned(F_RLEAF_LINV, MAP_IDENTITY, "rleaf_linv", -1, F.rleaf_linv, 1, nullptr, k_rleaf_linv, 0,
+            (int64_t)H.linv_tasks.size() / 2);
   return hipGetLastError();
 }
 
@@ -544,11 +546,11 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
-  for (int m = 0; m < M; ++m) run("rpost", m, F.rpost[m], k_rpost, P.nreg[m], m);
+  for (int m = 0; m < M; ++m) run.tuned(F_RPOST, MAP_IDENTITY, "rpost", m, F.rpost[m], 1, nullptr, k_rpost, 0, P.nreg[m], m);
   return hipGetLastError();
 }
 
@@ -557,17 +559,22 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, d
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
-  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
-  run.chunked("rleaf_q", -1, F.rleaf_q, nullptr, k_rleaf_q, nrow * (M + 1));
-  run("rleaf_sbar", -1, F.rleaf_sbar, k_rleaf_sbar, P.n_sig_tasks, theta);
+  run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1));
+  run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, F.rleaf_sbar, 1, nullptr, k_rleaf_sbar, 0, P.n_sig_tasks,
+            theta);
   if (M > 0) {
-    run.chunked("rrows_leaf", -1, F.rrows + F.rleaf_wbar, H.cut_rrows, k_rrows_leaf, nrow, theta);
-    run.grouped("rT_leaf", -1, F.rT_leaf, M * (M + 1) / 2, k_rT_leaf, P.nreg[M - 1] * (int64_t)(M * (M + 1) / 2));
+    run.tuned(F_RROWS, MAP_CHUNKED, "rrows_leaf", -1, F.rrows + F.rleaf_wbar, 1, H.cut_rrows, k_rrows_leaf, 0, nrow,
+              theta);
+    const int nkl = M * (M + 1) / 2;
+    run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, F.rT_leaf, nkl, nullptr, k_rT_leaf, 0, P.nreg[M - 1] * (int64_t)nkl);
     for (int m = M - 1; m >= 0; --m) {
-      run("rprior", m, F.rprior[m], k_rprior, P.nreg[m], theta, m);
-      if (m > 0) run.grouped("rT", m, F.rT[m], m * (m + 1) / 2, k_rT, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+      run.tuned(F_RPRIOR, MAP_IDENTITY, "rprior", m, F.rprior[m], 1, nullptr, k_rprior, 0, P.nreg[m], theta, m);
+      if (m > 0)
+        run.tuned(F_RT, MAP_GROUPED, "rT", m, F.rT[m], m * (m + 1) / 2, nullptr, k_rT, 0,
+                  P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   hipLaunchKernelGGL(k_gsum, dim3(nth), dim3(NT), 0, st, P, theta, out_grad, nslot);

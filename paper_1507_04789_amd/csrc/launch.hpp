@@ -46,6 +46,26 @@ __device__ __forceinline__ int64_t task_of(const TaskMap& m) {
   return m.t0 + g * m.G + (s % m.G);
 }
 
+// Tunable launch shapes.  Every batched launch belongs to a kernel family;
+// the plan's table picks, per family, how workgroups map to tasks (identity,
+// groups of related tasks on one XCD, or one contiguous chunk per XCD).  The
+// mapping only permutes tasks over workgroups, so results do not depend on it.
+enum Fam : int {
+  F_PRIOR, F_LEAF_ROWS, F_SIGMA, F_POTRF, F_TRSM, F_LEAF_REDUCE, F_POST, F_POST_REDUCE, F_RLEAF_V, F_RLEAF_LINV,
+  F_RPOST, F_RLEAF_Q, F_RLEAF_SBAR, F_RROWS, F_RT_LEAF, F_RPRIOR, F_RT, F_PREDICT, F_COUNT
+};
+enum Map : uint8_t { MAP_DEFAULT = 0, MAP_IDENTITY = 1, MAP_GROUPED = 2, MAP_CHUNKED = 3 };
+inline const char* fam_name(int f) {
+  static const char* n[F_COUNT] = {"prior", "leaf_rows", "leaf_sigma", "leaf_potrf", "leaf_trsm", "leaf_reduce",
+                                   "post", "post_reduce", "rleaf_v", "rleaf_linv", "rpost", "rleaf_q", "rleaf_sbar",
+                                   "rrows_leaf", "rT_leaf", "rprior", "rT", "predict"};
+  return (f >= 0 && f < F_COUNT) ? n[f] : "";
+}
+inline const char* map_name(int m) {
+  static const char* n[4] = {"default", "identity", "grouped", "chunked"};
+  return (m >= 0 && m < 4) ? n[m] : "";
+}
+
 struct ProfRecord {
   const char* name;
   int level;
@@ -78,16 +98,32 @@ struct Runner {
   hipStream_t st;
   bool plain;
   Profiler* prof;
+  const uint8_t* tune = nullptr;   // F_COUNT entries of Map, or null for the defaults
+  // tasks [t_begin, t_end) of family f: the table's mapping, else dflt;
+  // G is the family's natural group size, cut its chunk boundaries (or null)
+  template <class K, class... A>
+  void tuned(Fam f, Map dflt, const char* name, int level, double flops, int G, const int32_t* cut, K kern,
+             int64_t t_begin, int64_t t_end, A... args) const {
+    Map m = (tune && tune[f] != MAP_DEFAULT) ? (Map)tune[f] : dflt;
+    if (m == MAP_GROUPED && G <= 1) m = MAP_IDENTITY;
+    if (m == MAP_CHUNKED) {
+      chunked_range(name, level, flops, t_begin == 0 ? cut : nullptr, kern, t_begin, t_end, args...);
+    } else {
+      range(name, level, flops, m == MAP_GROUPED ? G : 1, kern, t_begin, t_end, args...);
+    }
+  }
   template <class K, class... A>
   void operator()(const char* name, int level, double flops, K kern, int64_t ntask, A... args) const {
     grouped(name, level, flops, 1, kern, ntask, args...);
   }
-  // one contiguous chunk of the task list per XCD (G = 0), cut at `cut`
-  // (equal task counts when null)
+  // tasks [t_begin, t_end) in one contiguous chunk per XCD (G = 0), cut at
+  // `cut` (relative to t_begin; equal task counts when null)
   template <class K, class... A>
-  void chunked(const char* name, int level, double flops, const int32_t* cut, K kern, int64_t ntask, A... args) const {
+  void chunked_range(const char* name, int level, double flops, const int32_t* cut, K kern, int64_t t_begin,
+                     int64_t t_end, A... args) const {
+    const int64_t ntask = t_end - t_begin;
     if (ntask <= 0) return;
-    TaskMap tm{0, ntask, 0, {}};
+    TaskMap tm{t_begin, ntask, 0, {}};
     int64_t widest = 0;
     for (int x = 0; x <= 8; ++x) tm.cut[x] = cut ? cut[x] : (int32_t)(ntask * x / 8);
     for (int x = 0; x < 8; ++x) widest = std::max<int64_t>(widest, tm.cut[x + 1] - tm.cut[x]);

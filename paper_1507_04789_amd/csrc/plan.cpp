@@ -202,14 +202,12 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return P->leaf_n[x] > P->leaf_n[y]; });
-  P->n_fac_big = 0;
   P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->linv_tasks.clear();
   P->pred_tasks.clear();
   for (int32_t i : order) {
     int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
     if (nb == 0) continue;
     P->fac_tasks.push_back(i);
-    if (nb >= 3) ++P->n_fac_big;
     for (int64_t bi = 0; bi < nb; ++bi)
       for (int64_t bj = 0; bj <= bi; ++bj) {
         P->sig_tasks.push_back(i); P->sig_tasks.push_back((int32_t)bi); P->sig_tasks.push_back((int32_t)bj);
@@ -327,6 +325,23 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   D.theta_stride = w;
   L.theta_stride = w;
 
+  // large-leaf counts and factorisation flop prefix sums in fac_tasks order
+  {
+    const int64_t nf = (int64_t)P->fac_tasks.size();
+    for (int t = 0; t < 16; ++t) P->nbig_thr[t] = 0;
+    P->fac_flops_pre.assign(nf + 1, 0.0);
+    P->trsm_flops_pre.assign(nf + 1, 0.0);
+    for (int64_t q = 0; q < nf; ++q) {
+      const int32_t lf = P->fac_tasks[q];
+      const int64_t nb = (P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T;
+      for (int t = 0; t < 16; ++t)
+        if (nb >= t) ++P->nbig_thr[t];
+      const double nr = P->leaf_n[lf];
+      P->fac_flops_pre[q + 1] = P->fac_flops_pre[q] + nr * nr * nr / 3.0;
+      P->trsm_flops_pre[q + 1] = P->trsm_flops_pre[q] + nr * nr * ((double)M * r + 1);
+    }
+  }
+
   // ---- algorithmic flop model (actual r, not the padded tile) ----
   // Counts multiply-adds as 2 flops; symmetric products count one triangle;
   // triangular solves and products count r^2 per right-hand side column.
@@ -360,10 +375,6 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     F.sigma += nr * nr * Mr;                                   // Sigma_R (SYRK)
     F.potrf += nr * nr * nr / 3.0;
     F.trsm += nr * nr * (Mr + 1);                              // L^{-1} [W^ | z]
-    if (nr > 2 * T) {
-      F.potrf_big += nr * nr * nr / 3.0;
-      F.trsm_big += nr * nr * (Mr + 1);
-    }
     F.leaf_reduce += nr * (Mr + 1) * (Mr + 1);                 // [W^ | z]' Sigma^{-1} [W^ | z]
     F.rleaf_v += nr * nr * (Mr + 1);                           // L^{-T} Y
     F.rleaf_linv += nr * nr * nr / 3.0;                        // L^{-1}

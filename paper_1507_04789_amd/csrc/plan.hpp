@@ -19,7 +19,6 @@ struct Profiler;    // defined in launch.hpp
 struct PhaseFlops {
   double prior[MAXL], post[MAXL], post_reduce[MAXL];
   double leaf_rows, sigma, potrf, trsm, leaf_reduce;
-  double potrf_big, trsm_big;   // part of potrf / trsm in leaves of >= 3 tiles
   double rpost[MAXL], rprior[MAXL], rT[MAXL];
   double rleaf_v, rleaf_linv, rleaf_q, rleaf_sbar, rleaf_wbar, rrows, rT_leaf;
   double predict;
@@ -58,7 +57,18 @@ struct mra_plan_s {
   std::vector<int64_t> pred_gidx;
   // task lists
   std::vector<int32_t> row_tasks, sig_tasks, fac_tasks, trsm_tasks, linv_tasks, pred_tasks;
-  int64_t n_fac_big = 0;   // leading fac_tasks (and M+1 trsm_tasks each) of leaves with >= 3 tiles
+  // fac_tasks are ordered largest leaf first; nbig_thr[t] counts the leaves
+  // of >= t tiles, fac_flops_pre / trsm_flops_pre are prefix sums of the
+  // algorithmic factorisation and solve flops in that order
+  int64_t nbig_thr[16] = {};
+  std::vector<double> fac_flops_pre, trsm_flops_pre;
+  // tuning: per kernel family launch mapping (mra::Map, 0 = default) and
+  // the tile count from which a leaf is factored on the side stream (0: none)
+  uint8_t tune[32] = {};
+  int32_t big_tiles = 3;
+  int64_t nbig() const { return big_tiles <= 0 ? 0 : nbig_thr[big_tiles < 15 ? big_tiles : 15]; }
+  double potrf_flops_big(int64_t k) const { return fac_flops_pre.empty() ? 0.0 : fac_flops_pre[k]; }
+  double trsm_flops_big(int64_t k) const { return trsm_flops_pre.empty() ? 0.0 : trsm_flops_pre[k]; }
   int32_t cut_rrows[9] = {};  // per-XCD chunks of row_tasks balancing the reverse row sweep's cost
   // layout
   mra::Layout lay;

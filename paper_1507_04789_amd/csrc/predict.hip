@@ -133,8 +133,9 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
 
 hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st) {
   const DevPlan& P = H.dp;
-  Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof};
-  run.chunked("predict", -1, H.pf.predict, nullptr, k_predict, (int64_t)H.pred_tasks.size() / 2, theta, mean, var);
+  Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, H.pf.predict, 1, nullptr, k_predict, 0,
+            (int64_t)H.pred_tasks.size() / 2, theta, mean, var);
   return hipGetLastError();
 }
 

@@ -105,3 +105,21 @@ def test_rejects_unknown_flags():
     g = np.random.default_rng(4)
     with pytest.raises(MRAError):
         Plan(g.random((100, 2)), M=1, J=4, r=4, cov="exponential", flags=64)
+
+
+def test_tuning_table_roundtrip():
+    g = np.random.default_rng(5)
+    p = Plan(g.random((500, 2)), M=2, J=4, r=9, cov="exponential")
+    t = p.tuning()
+    assert t["big_leaf_tiles"] == 3 and set(t["families"].values()) == {"default"}
+    t["families"]["leaf_rows"] = "identity"
+    t["families"]["rT_leaf"] = "chunked"
+    t["big_leaf_tiles"] = 0
+    p.set_tuning(t)
+    u = p.tuning()
+    assert u["families"]["leaf_rows"] == "identity" and u["families"]["rT_leaf"] == "chunked"
+    assert u["big_leaf_tiles"] == 0
+    with pytest.raises(MRAError):
+        p.set_tuning({"families": {"post": "sideways"}})
+    with pytest.raises(MRAError):
+        p.set_tuning({"big_leaf_tiles": -2})
