@@ -153,7 +153,7 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
 
 // Y = L_Sigma^{-1} X for one column plane of one leaf (forward substitution
 // by tiles with the inverted diagonal tiles)
-__global__ __launch_bounds__(NT) void k_leaf_trsm(DevPlan P, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];

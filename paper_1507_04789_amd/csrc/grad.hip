@@ -71,7 +71,7 @@ __device__ void write_partial(const DevPlan& P, double* S, int64_t slot, double 
 
 // ---------------------------------------------------------------- posterior
 // region (m, i), top-down: G^{m,l} = Xbar_l, G^{m,m} = Pbar, wbar^m = xbar_w
-__global__ __launch_bounds__(NT) void k_rpost(DevPlan P, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, TaskMap tm) {
 }
 
 // tile column j of L_Sigma^{-1} (forward substitution of the identity)
-__global__ __launch_bounds__(NT) void k_rleaf_linv(DevPlan P, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -334,7 +334,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
 
 // leaf rows: the cotangent of W^_R from the leaf step is 2 Q - 2 Sigma-bar W^_R
 // (computed here as the first product segments), then the reverse sweep
-__global__ __launch_bounds__(NT, 2) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
+__global__ __launch_bounds__(NT, 3) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
