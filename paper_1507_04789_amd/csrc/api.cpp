@@ -48,15 +48,28 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
 hipError_t ensure_side(mra_plan_s* H) {
   if (H->side_stream) return hipSuccess;
   hipStream_t s2;
-  hipEvent_t a, b;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipError_t e;
-  if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) return e;
-  if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess) return e;
-  if ((e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) return e;
+  for (int i = 0; i < 4; ++i)
+    if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      return e;
+    }
+  if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) {
+    for (int j = 0; j < 4; ++j) (void)hipEventDestroy(ev[j]);
+    return e;
+  }
   H->side_stream = s2;
-  H->ev_fork = a;
-  H->ev_join = b;
+  H->ev_fork = ev[0];
+  H->ev_big = ev[1];
+  H->ev_fork2 = ev[2];
+  H->ev_join = ev[3];
   return hipSuccess;
+}
+
+Side side_of(const mra_plan_s* H) {
+  return Side{(hipStream_t)H->side_stream, (hipEvent_t)H->ev_fork, (hipEvent_t)H->ev_big, (hipEvent_t)H->ev_fork2,
+              (hipEvent_t)H->ev_join};
 }
 
 }  // namespace
@@ -128,21 +141,20 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   const bool overlap = !(H->cfg.flags & MRA_PLAIN);
   hipError_t e;
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
-  if (overlap)
-    e = launch_forward_front(*H, y, theta, nth, st, (hipStream_t)H->side_stream, H->ev_fork, H->ev_join);
-  else
-    e = launch_forward_front(*H, y, theta, nth, st);
-  if (e != hipSuccess) return e;
-  hipStream_t s2 = overlap ? (hipStream_t)H->side_stream : st;
-  if (overlap) {
-    if ((e = hipEventRecord((hipEvent_t)H->ev_fork, st)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s2, (hipEvent_t)H->ev_fork, 0)) != hipSuccess) return e;
+  const Side sd = side_of(H);
+  const Side* side = overlap ? &sd : nullptr;
+  if ((e = launch_forward_front(*H, y, theta, nth, st, side)) != hipSuccess) return e;
+  if (side) {
+    // leaf solves on the side stream, after the small leaves (fork2) and,
+    // in stream order, after the large ones
+    if ((e = hipEventRecord(sd.fork2, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(sd.s, sd.fork2, 0)) != hipSuccess) return e;
   }
-  if ((e = launch_grad_leafsolve(*H, nth, s2)) != hipSuccess) return e;
-  if (overlap && (e = hipEventRecord((hipEvent_t)H->ev_join, s2)) != hipSuccess) return e;
-  if ((e = launch_forward_back(*H, nth, ll, st)) != hipSuccess) return e;
+  if ((e = launch_grad_leafsolve(*H, nth, side ? sd.s : st)) != hipSuccess) return e;
+  if (side && (e = hipEventRecord(sd.join, sd.s)) != hipSuccess) return e;
+  if ((e = launch_forward_back(*H, nth, ll, st, side)) != hipSuccess) return e;
   if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
-  if (overlap && (e = hipStreamWaitEvent(st, (hipEvent_t)H->ev_join, 0)) != hipSuccess) return e;
+  if (side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
   return launch_grad_rest(*H, theta, nth, g, st);
 }
 
@@ -279,6 +291,7 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
             up(L.g_fact, P->fac_tasks.data(), P->fac_tasks.size() * 4) &&
             up(L.g_trst, P->trsm_tasks.data(), P->trsm_tasks.size() * 4) &&
             up(L.g_lint, P->linv_tasks.data(), P->linv_tasks.size() * 4) &&
+            up(L.g_rord, P->reduce_order.data(), P->reduce_order.size() * 4) &&
             up(L.g_pxy, P->pred_xy.data(), P->pred_xy.size() * 8) &&
             up(L.g_pgidx, P->pred_gidx.data(), P->pred_gidx.size() * 8) &&
             up(L.g_pt, P->pred_tasks.data(), P->pred_tasks.size() * 4) &&
@@ -298,6 +311,7 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   D.fac_tasks = (const int32_t*)(g + L.g_fact);
   D.trsm_tasks = (const int32_t*)(g + L.g_trst);
   D.linv_tasks = (const int32_t*)(g + L.g_lint);
+  D.reduce_order = (const int32_t*)(g + L.g_rord);
   D.pred_xy = (const double*)(g + L.g_pxy);
   D.pred_gidx = (const int64_t*)(g + L.g_pgidx);
   D.pred_tasks = (const int32_t*)(g + L.g_pt);
@@ -321,12 +335,11 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   const bool overlap = !(P->cfg.flags & MRA_PLAIN);
   if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const GraphKey key{0, n_theta, {d_y, d_theta, d_loglik, nullptr, nullptr}};
+  const Side sd = side_of(P);
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
-    hipError_t e = overlap ? launch_forward_front(*P, d_y, d_theta, n_theta, q, (hipStream_t)P->side_stream,
-                                                  P->ev_fork, P->ev_join)
-                           : launch_forward_front(*P, d_y, d_theta, n_theta, q);
+    hipError_t e = launch_forward_front(*P, d_y, d_theta, n_theta, q, overlap ? &sd : nullptr);
     if (e != hipSuccess) return e;
-    return launch_forward_back(*P, n_theta, d_loglik, q);
+    return launch_forward_back(*P, n_theta, d_loglik, q, overlap ? &sd : nullptr);
   }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
@@ -422,12 +435,11 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
   const bool prof = P->prof && P->prof->enabled;
   if (prof) P->prof->enabled = false;
   P->last_nth = n_theta;
+  const Side sd = side_of(P);
   auto call = [&]() -> hipError_t {
     if (grad) return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, st);
-    hipError_t e = overlap ? launch_forward_front(*P, d_y, d_theta, n_theta, st, (hipStream_t)P->side_stream,
-                                                  P->ev_fork, P->ev_join)
-                           : launch_forward_front(*P, d_y, d_theta, n_theta, st);
-    return e != hipSuccess ? e : launch_forward_back(*P, n_theta, d_loglik, st);
+    hipError_t e = launch_forward_front(*P, d_y, d_theta, n_theta, st, overlap ? &sd : nullptr);
+    return e != hipSuccess ? e : launch_forward_back(*P, n_theta, d_loglik, st, overlap ? &sd : nullptr);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -560,8 +572,8 @@ void mra_destroy(mra_plan_t P) {
     (void)hipStreamSynchronize((hipStream_t)P->side_stream);
     (void)hipStreamDestroy((hipStream_t)P->side_stream);
   }
-  if (P->ev_fork) (void)hipEventDestroy((hipEvent_t)P->ev_fork);
-  if (P->ev_join) (void)hipEventDestroy((hipEvent_t)P->ev_join);
+  for (void* ev : {P->ev_fork, P->ev_big, P->ev_fork2, P->ev_join})
+    if (ev) (void)hipEventDestroy((hipEvent_t)ev);
   if (P->graphs) {
     P->graphs->clear();
     if (P->graphs->cap) (void)hipStreamDestroy(P->graphs->cap);

@@ -32,6 +32,7 @@ struct DevPlan {
   const int32_t* fac_tasks;  // [n_fac_tasks] nonempty leaves, largest first
   const int32_t* trsm_tasks; // [n_trsm_tasks][2] (leaf, column plane 0..M)
   const int32_t* linv_tasks; // [n_linv_tasks][2] (leaf, tile column j)
+  const int32_t* reduce_order;  // level-(M-1) regions in leaf-product order
   int64_t n_sig_tasks, n_row_tasks;
   const double* pred_xy;     // [ppad][2]
   const int64_t* pred_gidx;  // [ppad]

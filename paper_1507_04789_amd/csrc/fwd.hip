@@ -197,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
   const int M = P.M;
   const int nkl = M * (M + 1) / 2;
   const int64_t gid = tk0;
-  const int64_t pidx = gid / nkl;
+  const int64_t pidx = P.reduce_order[gid / nkl];
   const int kl = (int)(gid % nkl);
   int k, l;
   kl_split(kl, k, l);
@@ -383,12 +383,12 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 
 // ------------------------------------------------------------------ launches
 // init, prior levels and the leaf factorisation (everything the reverse
-// pass's leaf solves depend on)
-// With a side stream, the few leaves of three or more tiles are factored and
-// solved there while the many small leaves proceed on `st`; `st` waits for
-// them before returning (the leaf products need every leaf).
+// pass's leaf solves depend on).  With a side stream, the leaves of
+// big_tiles tiles or more are factored and solved there while the small
+// leaves proceed on `st`; side->big marks their completion and is awaited in
+// launch_forward_back.
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                hipStream_t side, void* ev_fork, void* ev_join) {
+                                const Side* side) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -407,37 +407,48 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   const int64_t nbig = side ? H.nbig() : 0;
   if (nbig > 0) {
     hipError_t e;
-    if ((e = hipEventRecord((hipEvent_t)ev_fork, st)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(side, (hipEvent_t)ev_fork, 0)) != hipSuccess) return e;
-    Runner rs{P, nth, side, false, H.prof, H.tune};
+    if ((e = hipEventRecord(side->fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side->s, side->fork, 0)) != hipSuccess) return e;
+    Runner rs{P, nth, side->s, false, H.prof, H.tune};
     const double fpb = H.potrf_flops_big(nbig), ftb = H.trsm_flops_big(nbig);
     rs.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf_big", -1, fpb, 1, nullptr, k_leaf_potrf, 0, nbig);
     rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm, 0, nbig * (M + 1));
-    if ((e = hipEventRecord((hipEvent_t)ev_join, side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(side->big, side->s)) != hipSuccess) return e;
   }
   run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, F.potrf - H.potrf_flops_big(nbig), 1, nullptr, k_leaf_potrf, nbig,
             nfac);
   run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm,
             nbig * (M + 1), ntrsm);
-  if (nbig > 0) {
-    hipError_t e = hipStreamWaitEvent(st, (hipEvent_t)ev_join, 0);
-    if (e != hipSuccess) return e;
-  }
   return hipGetLastError();
 }
 
-// leaf products, posterior recursion and the log-likelihood
-hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st) {
+// leaf products, posterior recursion and the log-likelihood.  With large
+// leaves on the side stream, the parents whose children are all small go
+// first; the main stream then waits for the large leaves.
+hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st, const Side* side) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  const bool split = side && H.nbig() > 0;
   if (M == 0) {
+    if (split) {
+      hipError_t e = hipStreamWaitEvent(st, side->big, 0);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
     const int nkl = M * (M + 1) / 2;
-    run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, F.leaf_reduce, nkl, nullptr, k_leaf_reduce, 0,
-              P.nreg[M - 1] * (int64_t)nkl);
+    const int64_t ntask = P.nreg[M - 1] * (int64_t)nkl;
+    const int64_t cut = split ? H.nsmall() * nkl : ntask;
+    const double f0 = ntask ? F.leaf_reduce * (double)cut / (double)ntask : 0.0;
+    run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, f0, nkl, nullptr, k_leaf_reduce, 0, cut);
+    if (split) {
+      hipError_t e = hipStreamWaitEvent(st, side->big, 0);
+      if (e != hipSuccess) return e;
+      run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce_big", -1, F.leaf_reduce - f0, nkl, nullptr, k_leaf_reduce,
+                cut, ntask);
+    }
     for (int m = M - 1; m >= 0; --m) {
       run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, P.nreg[m], m, out_loglik);
       if (m > 0)

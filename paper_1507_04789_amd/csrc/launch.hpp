@@ -172,9 +172,19 @@ struct Runner {
 
 hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* theta, int nth, double* out_loglik,
                           hipStream_t st);
+// A second stream for work that only needs the leaf factors.  Large leaves
+// (big_tiles tiles or more) are factored on it, forked after the Sigma
+// tiles (fork) and awaited by the main stream before the leaf products of
+// their parents (big); the reverse pass's leaf solves follow on it (fork2,
+// join).  A null Side runs everything on the main stream.
+struct Side {
+  hipStream_t s;
+  hipEvent_t fork, big, fork2, join;
+};
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                hipStream_t side = nullptr, void* ev_fork = nullptr, void* ev_join = nullptr);
-hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st);
+                                const Side* side = nullptr);
+hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st,
+                               const Side* side = nullptr);
 hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st);
 hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st);
 hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st);

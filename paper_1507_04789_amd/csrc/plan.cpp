@@ -246,6 +246,26 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   }
   if (P->npad > INT32_MAX || P->ppad > INT32_MAX) return MRA_EINVAL;
 
+  // leaf-product order of the level-(M-1) regions
+  P->reduce_order.clear();
+  for (int t = 0; t < 16; ++t) P->nsmall_thr[t] = 0;
+  if (M > 0) {
+    const int64_t np = P->nreg[M - 1];
+    std::vector<int64_t> maxnb(np, 0);
+    for (int64_t q = 0; q < np; ++q)
+      for (int c = 0; c < J; ++c) {
+        const int64_t lf = q * J + c;
+        maxnb[q] = std::max<int64_t>(maxnb[q], (P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T);
+      }
+    P->reduce_order.resize(np);
+    std::iota(P->reduce_order.begin(), P->reduce_order.end(), 0);
+    std::stable_sort(P->reduce_order.begin(), P->reduce_order.end(),
+                     [&](int32_t x, int32_t y) { return maxnb[x] < maxnb[y]; });
+    for (int t = 0; t < 16; ++t)
+      for (int64_t q = 0; q < np; ++q)
+        if (maxnb[q] < t) ++P->nsmall_thr[t];
+  }
+
   // ---- geometry arena layout (bytes, 256-aligned) ----
   Layout& L = P->lay;
   size_t off = 0;
@@ -262,6 +282,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.g_fact = take(std::max<size_t>(P->fac_tasks.size(), 1) * 4);
   L.g_trst = take(std::max<size_t>(P->trsm_tasks.size(), 1) * 4);
   L.g_lint = take(std::max<size_t>(P->linv_tasks.size(), 1) * 4);
+  L.g_rord = take(std::max<size_t>(P->reduce_order.size(), 1) * 4);
   L.g_pxy = take(P->pred_xy.size() * 8);
   L.g_pgidx = take(P->pred_gidx.size() * 8);
   L.g_pt = take(std::max<size_t>(P->pred_tasks.size(), 1) * 4);

@@ -26,7 +26,7 @@ struct PhaseFlops {
 
 struct Layout {
   // geometry arena (byte offsets)
-  size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst, g_lint;
+  size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst, g_lint, g_rord;
   size_t g_pxy, g_pgidx, g_pt, g_pleafn, g_ppoff, geom_bytes;
   // work arena (doubles per theta slice)
   int64_t theta_stride;
@@ -66,6 +66,12 @@ struct mra_plan_s {
   // the tile count from which a leaf is factored on the side stream (0: none)
   uint8_t tune[32] = {};
   int32_t big_tiles = 3;
+  // level-(M-1) regions ordered by their largest child's tile count
+  // (ascending, tree order within); nsmall_thr[t] leads with children all
+  // below t tiles, whose leaf products need none of the side stream's leaves
+  std::vector<int32_t> reduce_order;
+  int64_t nsmall_thr[16] = {};
+  int64_t nsmall() const { return nsmall_thr[big_tiles < 15 ? big_tiles : 15]; }
   int64_t nbig() const { return big_tiles <= 0 ? 0 : nbig_thr[big_tiles < 15 ? big_tiles : 15]; }
   double potrf_flops_big(int64_t k) const { return fac_flops_pre.empty() ? 0.0 : fac_flops_pre[k]; }
   double trsm_flops_big(int64_t k) const { return trsm_flops_pre.empty() ? 0.0 : trsm_flops_pre[k]; }
@@ -84,8 +90,10 @@ struct mra_plan_s {
   mra::PhaseFlops pf;
   mra::Profiler* prof = nullptr;
   void* side_stream = nullptr;   // hipStream_t for work overlapped with the main stream
-  void* ev_fork = nullptr;       // hipEvent_t
-  void* ev_join = nullptr;
+  void* ev_fork = nullptr;       // hipEvent_t: main -> side, large leaves' factorisation
+  void* ev_big = nullptr;        //   side -> main, large leaves done
+  void* ev_fork2 = nullptr;      //   main -> side, reverse-pass leaf solves
+  void* ev_join = nullptr;       //   side -> main, leaf solves done
   int32_t last_nth = 1;
 };
 
