@@ -101,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, Ta
   acc_store(acc, S + P.off_sig + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT, T);
 }
 
-// blocked right-looking Cholesky of one leaf's Sigma (tiles in place), the
+// blocked left-looking Cholesky of one leaf's Sigma (tiles in place), the
 // inverses of its diagonal tiles, and d_R = log|Sigma_R|
 __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
@@ -120,30 +120,33 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
   double logdet = 0.0;
   bool ok = true;
   Acc acc;
-  for (int kb = 0; kb < nb; ++kb) {
-    double* Dk = base + ((int64_t)kb * nb + kb) * TT;
-    tile_to_lds(Dk, T, lds);
+  // left-looking by tile column: each tile takes all its updates from the
+  // finished columns as one chain of products, then its own step
+  for (int jb = 0; jb < nb; ++jb) {
+    double* Dj = base + ((int64_t)jb * nb + jb) * TT;
+    const double* Lj = base + (int64_t)jb * nb * TT;   // row jb of tiles
+    acc_load(acc, Dj, T);
+    gemm_segs(acc, jb, [&](int k) { return seg<Op::N, Op::T>(Lj + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); },
+              lds);
+    acc_to_lds(acc, lds);
     __syncthreads();
-    ok = potrf_trtri(lds, lds_x, dinv + (int64_t)kb * TT) && ok;
-    logdet += 2.0 * logdiag_lds(lds, min(T, nR - kb * T), red);
-    lds_to_global(lds, Dk);
+    ok = potrf_trtri(lds, lds_x, dinv + (int64_t)jb * TT) && ok;
+    logdet += 2.0 * logdiag_lds(lds, min(T, nR - jb * T), red);
+    lds_to_global(lds, Dj);
     __syncthreads();
-    for (int ib = kb + 1; ib < nb; ++ib) {
-      double* X = base + ((int64_t)ib * nb + kb) * TT;
-      acc_zero(acc);
-      gemm<Op::N, Op::T>(acc, X, T, dinv + (int64_t)kb * TT, T, T, 1.0, lds);
+    for (int ib = jb + 1; ib < nb; ++ib) {
+      double* X = base + ((int64_t)ib * nb + jb) * TT;
+      const double* Li = base + (int64_t)ib * nb * TT;
+      acc_load(acc, X, T);
+      gemm_segs(acc, jb,
+                [&](int k) { return seg<Op::N, Op::T>(Li + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); }, lds);
       acc_store(acc, X, T);
+      __syncthreads();
+      acc_zero(acc);
+      gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
+      acc_store(acc, X, T);
+      __syncthreads();
     }
-    __syncthreads();
-    for (int jb = kb + 1; jb < nb; ++jb)
-      for (int ib = jb; ib < nb; ++ib) {
-        double* X = base + ((int64_t)ib * nb + jb) * TT;
-        acc_load(acc, X, T);
-        gemm<Op::N, Op::T>(acc, base + ((int64_t)ib * nb + kb) * TT, T, base + ((int64_t)jb * nb + kb) * TT, T, T,
-                           -1.0, lds);
-        acc_store(acc, X, T);
-      }
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     S[P.off_leafd + leaf] = logdet;
