@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, Ta
   const double* W = S + P.off_wobs;
   gemm_segs(acc, P.M,
             [&](int k) { return seg<Op::N, Op::T>(W + k * P.plane + pi * T, T, W + k * P.plane + pj * T, T, -1.0); },
-            lds, round16(nvi));
+            lds, round16(nvi), round16(nvj));
   acc_store(acc, S + P.off_sig + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT, T);
 }
 

@@ -275,6 +275,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   const int nR = P.leaf_n[leaf];
   const int64_t pi = poff + (int64_t)T * bi, pj = poff + (int64_t)T * bj;
   const double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
+  const int nvi = min(T, nR - T * bi), nvj = min(T, nR - T * bj);
   Acc acc;
   acc_zero(acc);
   gemm_segs(acc, P.M + 1 + (nb - bi), [&](int q) {
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
       return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0);
     const int kb = bi + q - (P.M + 1);
     return seg<Op::T, Op::N>(Li + ((int64_t)kb * nb + bi) * TT, T, Li + ((int64_t)kb * nb + bj) * TT, T, -0.5);
-  }, lds);
+  }, lds, round16(nvi), round16(nvj));
   double* out = S + P.off_sbar + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT;
   acc_store(acc, out, T);
   if (bi == bj) {
@@ -290,8 +291,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
     acc_load(acc, out, T);
   }
   double g[3] = {0.0, 0.0, 0.0};
-  acc_cov_contract(acc, P.obs_xy + 2 * pi, min(T, nR - T * bi), P.obs_xy + 2 * pj, min(T, nR - T * bj), cp,
-                   bi == bj, g);
+  acc_cov_contract(acc, P.obs_xy + 2 * pi, nvi, P.obs_xy + 2 * pj, nvj, cp, bi == bj, g);
   const double wgt = (bi == bj) ? 1.0 : 2.0;   // lower tiles stand for both triangles
   g[0] *= wgt;
   g[1] *= wgt;

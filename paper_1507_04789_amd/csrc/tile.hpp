@@ -141,9 +141,10 @@ __device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const d
 // multi-segment GEMM: acc += sum_s alpha_s * opA_s(A_s) * opB_s(B_s), each
 // segment a 64x64xK_s product (K_s = 16 * nch_s, nch_s in 1..4).  The
 // prefetch pipeline of gemm() runs across segment boundaries, so a chain of
-// short products pays the global-memory latency once.  Row blocks of the
-// output at or beyond `mrows` are not multiplied (their operand rows are
-// padding).
+// short products pays the global-memory latency once.  16-row (16-column)
+// blocks of the output at or beyond `mrows` (`ncols`) are not multiplied:
+// their operand rows (columns) are padding, and the accumulator keeps its
+// value there.
 // ---------------------------------------------------------------------------
 struct Seg {
   const double* A;
@@ -174,13 +175,14 @@ __device__ __forceinline__ void stash_rt(double* s, d4 v, bool kmajor) {
 }
 
 template <class F>
-__device__ __forceinline__ void gemm_segs(Acc& acc, int nseg, F getseg, double* lds, int mrows = T) {
+__device__ __forceinline__ void gemm_segs(Acc& acc, int nseg, F getseg, double* lds, int mrows = T, int ncols = T) {
   if (nseg <= 0) return;
   const int w = wave_id(), l = lane_id();
   const int ia = 32 * (w >> 1) + (l & 15);
   const int jb = 32 * (w & 1) + (l & 15);
   const int kr = l >> 4;
   const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
+  const bool col0 = 32 * (w & 1) < ncols, col1 = 32 * (w & 1) + 16 < ncols;
   int s = 0, cs = 0;
   Seg cur = getseg(0);
   d4 va = fetch_rt(cur.A, cur.lda, 0, cur.ak);
@@ -215,13 +217,13 @@ __device__ __forceinline__ void gemm_segs(Acc& acc, int nseg, F getseg, double* 
       const double b0 = rb[jb], b1 = rb[jb + 16];
       if (row0) {
         const double a0 = alpha_c * ra[ia];
-        acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
-        acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+        if (col0) acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+        if (col1) acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
       }
       if (row1) {
         const double a1 = alpha_c * ra[ia + 16];
-        acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
-        acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+        if (col0) acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+        if (col1) acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
       }
     }
     if (!more) {
