@@ -18,6 +18,7 @@ constexpr int COV_MATERN32 = 1;
 
 struct CovP {
   double s2, kappa, tau2;
+  double ikappa;   // 1 / kappa: h = dist * ikappa avoids a division per entry
   int kind;
 };
 
@@ -25,6 +26,7 @@ __device__ __forceinline__ CovP load_cov(const double* theta, int kind) {
   CovP c;
   c.s2 = exp(theta[0]);
   c.kappa = exp(theta[1]);
+  c.ikappa = exp(-theta[1]);
   c.tau2 = exp(theta[2]);
   c.kind = kind;
   return c;
@@ -37,7 +39,7 @@ __device__ __forceinline__ double dist2(const double* X, int i, const double* Y,
 }
 
 __device__ __forceinline__ double cov_val(double dist, const CovP& c) {
-  double h = dist / c.kappa;
+  double h = dist * c.ikappa;
   if (c.kind == COV_MATERN32) {
     double a = 1.7320508075688772 * h;
     return c.s2 * ((1.0 + a) * exp(-a));
@@ -47,12 +49,12 @@ __device__ __forceinline__ double cov_val(double dist, const CovP& c) {
 
 // value and d/dlog kappa
 __device__ __forceinline__ void cov_val_dk(double dist, const CovP& c, double& v, double& dk) {
-  double h = dist / c.kappa;
+  double h = dist * c.ikappa;
   if (c.kind == COV_MATERN32) {
     double a = 1.7320508075688772 * h;
     double e = exp(-a);
     v = c.s2 * ((1.0 + a) * e);
-    dk = c.s2 * (3.0 * h * h * e);
+    dk = c.s2 * (a * a * e);   // 3 h^2 = a^2
   } else {
     double e = exp(-h);
     v = c.s2 * e;
