@@ -292,6 +292,10 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
             up(L.g_trst, P->trsm_tasks.data(), P->trsm_tasks.size() * 4) &&
             up(L.g_lint, P->linv_tasks.data(), P->linv_tasks.size() * 4) &&
             up(L.g_rord, P->reduce_order.data(), P->reduce_order.size() * 4) &&
+            up(L.g_slotp, P->slot_prior.data(), P->slot_prior.size() * 4) &&
+            up(L.g_slotq, P->slot_post.data(), P->slot_post.size() * 4) &&
+            up(L.g_actp, P->act_prior.data(), P->act_prior.size() * 4) &&
+            up(L.g_actq, P->act_post.data(), P->act_post.size() * 4) &&
             up(L.g_pxy, P->pred_xy.data(), P->pred_xy.size() * 8) &&
             up(L.g_pgidx, P->pred_gidx.data(), P->pred_gidx.size() * 8) &&
             up(L.g_pt, P->pred_tasks.data(), P->pred_tasks.size() * 4) &&
@@ -312,6 +316,10 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   D.trsm_tasks = (const int32_t*)(g + L.g_trst);
   D.linv_tasks = (const int32_t*)(g + L.g_lint);
   D.reduce_order = (const int32_t*)(g + L.g_rord);
+  D.slot_prior = (const int32_t*)(g + L.g_slotp);
+  D.slot_post = (const int32_t*)(g + L.g_slotq);
+  D.act_prior = (const int32_t*)(g + L.g_actp);
+  D.act_post = (const int32_t*)(g + L.g_actq);
   D.pred_xy = (const double*)(g + L.g_pxy);
   D.pred_gidx = (const int64_t*)(g + L.g_pgidx);
   D.pred_tasks = (const int32_t*)(g + L.g_pt);

@@ -7,8 +7,13 @@ namespace mra {
 
 __device__ __forceinline__ double* slice(const DevPlan& P, int th) { return P.work + (int64_t)th * P.theta_stride; }
 
+// Region storage is compact over the active regions of a level (regions
+// with nothing below them are pruned); callers only pass active regions.
 __device__ __forceinline__ double* prior_reg(const DevPlan& P, double* S, int m, int64_t i) {
-  return S + P.prior_off[m] + i * (int64_t)(m + 2) * TT;
+  return S + P.prior_off[m] + (int64_t)P.slot_prior[P.reg_base[m] + i] * (m + 2) * TT;
+}
+__device__ __forceinline__ bool post_active(const DevPlan& P, int m, int64_t i) {
+  return P.slot_post[P.reg_base[m] + i] >= 0;
 }
 __device__ __forceinline__ const double* knots_of(const DevPlan& P, int m, int64_t i) {
   return P.knot_xy + (P.reg_base[m] + i) * (2 * T);
@@ -40,7 +45,7 @@ struct Post {
 };
 __device__ __forceinline__ Post post_of(const DevPlan& P, double* S, int m, int64_t i) {
   Post p;
-  p.base = S + P.post_off[m] + i * P.post_stride[m];
+  p.base = S + P.post_off[m] + (int64_t)P.slot_post[P.reg_base[m] + i] * P.post_stride[m];
   p.m = m;
   return p;
 }
@@ -90,7 +95,7 @@ struct Grad {
 };
 __device__ __forceinline__ Grad grad_of(const DevPlan& P, double* S, int m, int64_t i) {
   Grad g;
-  g.base = S + P.grad_off[m] + i * P.grad_stride[m];
+  g.base = S + P.grad_off[m] + (int64_t)P.slot_post[P.reg_base[m] + i] * P.grad_stride[m];
   g.m = m;
   return g;
 }

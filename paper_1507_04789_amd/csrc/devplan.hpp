@@ -32,7 +32,11 @@ struct DevPlan {
   const int32_t* fac_tasks;  // [n_fac_tasks] nonempty leaves, largest first
   const int32_t* trsm_tasks; // [n_trsm_tasks][2] (leaf, column plane 0..M)
   const int32_t* linv_tasks; // [n_linv_tasks][2] (leaf, tile column j)
-  const int32_t* reduce_order;  // level-(M-1) regions in leaf-product order
+  const int32_t* reduce_order;  // active level-(M-1) regions in leaf-product order
+  const int32_t* slot_prior;    // [n_internal] compact prior index within the level, -1 if pruned
+  const int32_t* slot_post;     // [n_internal] compact posterior / reverse index, -1 if pruned
+  const int32_t* act_prior;     // active regions (prior), level by level
+  const int32_t* act_post;      // active regions (posterior and reverse), level by level
   int64_t n_sig_tasks, n_row_tasks;
   const double* pred_xy;     // [ppad][2]
   const int64_t* pred_gidx;  // [ppad]
@@ -43,6 +47,7 @@ struct DevPlan {
   // level tables
   int64_t nreg[MAXL];        // J^m
   int64_t reg_base[MAXL];    // index of the first region of level m among internal regions
+  int64_t act_prior_off[MAXL + 1], act_post_off[MAXL + 1];   // level offsets into act_prior / act_post
   int64_t prior_off[MAXL];   // offset (doubles) of level m prior storage in a theta slice
   int64_t post_off[MAXL];    // offset of level m posterior storage
   int64_t post_stride[MAXL]; // doubles per region of level m posterior storage

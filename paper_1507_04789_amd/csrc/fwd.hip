@@ -46,7 +46,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double lds_x[T * PLD];
   const int th = blockIdx.y;
-  const int64_t i = tk0;
+  const int64_t i = P.act_prior[P.act_prior_off[m] + tk0];
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
   double* reg = prior_reg(P, S, m, i);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   __shared__ double lds_x[T * PLD];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t i = tk0;
+  const int64_t i = P.act_post[P.act_post_off[m] + tk0];
   double* S = slice(P, th);
   Post po = post_of(P, S, m, i);
   tile_to_lds(po.A(m, m), T, lds);
@@ -320,25 +320,30 @@ __global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, TaskMap tm
   const int th = blockIdx.y;
   const int nkl = m * (m + 1) / 2;       // blocks k >= l <= m-1
   const int64_t gid = tk0;
-  const int64_t pidx = gid / nkl;
+  const int64_t pidx = P.act_post[P.act_post_off[m - 1] + gid / nkl];
   const int kl = (int)(gid % nkl);
   int k, l;
   kl_split(kl, k, l);
   double* S = slice(P, th);
   Post pp = post_of(P, S, m - 1, pidx);
+  // children with observations below them (the others contribute zero)
+  int64_t ch[8];
+  int nch = 0;
+  for (int c = 0; c < P.J; ++c)
+    if (post_active(P, m, pidx * P.J + c)) ch[nch++] = pidx * P.J + c;
   Acc acc;
   acc_zero(acc);
-  for (int c = 0; c < P.J; ++c) acc_load(acc, post_of(P, S, m, pidx * P.J + c).A(k, l), T, true);
-  gemm_segs(acc, P.J, [&](int c) {
-    Post pc = post_of(P, S, m, pidx * P.J + c);
+  for (int c = 0; c < nch; ++c) acc_load(acc, post_of(P, S, m, ch[c]).A(k, l), T, true);
+  gemm_segs(acc, nch, [&](int c) {
+    Post pc = post_of(P, S, m, ch[c]);
     return seg<Op::T, Op::N>(pc.Z(k), T, pc.Z(l), T, -1.0);
   }, lds);
   acc_store(acc, pp.A(k, l), T);
   if (k == l) {      // w^k_P = sum_c (w^k_c - Z^k_c' z_c)
     double w = 0.0;
     const int col = threadIdx.x & 63;
-    for (int c = 0; c < P.J; ++c) {
-      Post pc = post_of(P, S, m, pidx * P.J + c);
+    for (int c = 0; c < nch; ++c) {
+      Post pc = post_of(P, S, m, ch[c]);
       const double* Zk = pc.Z(k);
       const double* zw = pc.zw();
       if (wave_id() == 0) w += pc.omega(k)[col];
@@ -349,8 +354,8 @@ __global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, TaskMap tm
   }
   if (kl == 0 && threadIdx.x == 0) {
     double dsum = 0.0, usum = 0.0;
-    for (int c = 0; c < P.J; ++c) {
-      Post pc = post_of(P, S, m, pidx * P.J + c);
+    for (int c = 0; c < nch; ++c) {
+      Post pc = post_of(P, S, m, ch[c]);
       dsum += *pc.d();
       usum += *pc.u();
     }
@@ -401,7 +406,7 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
   for (int m = 0; m < M; ++m)
-    run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, P.nreg[m], theta, m);
+    run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, H.nact_prior(m), theta, m);
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,
             (int64_t)H.row_tasks.size() / 2, theta);
   run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, F.sigma, 1, nullptr, k_sigma, 0, (int64_t)H.sig_tasks.size() / 3,
@@ -442,7 +447,7 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
     const int nkl = M * (M + 1) / 2;
-    const int64_t ntask = P.nreg[M - 1] * (int64_t)nkl;
+    const int64_t ntask = (int64_t)H.reduce_order.size() * nkl;
     const int64_t cut = split ? H.nsmall() * nkl : ntask;
     const double f0 = ntask ? F.leaf_reduce * (double)cut / (double)ntask : 0.0;
     run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, f0, nkl, nullptr, k_leaf_reduce, 0, cut);
@@ -453,10 +458,10 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
                 cut, ntask);
     }
     for (int m = M - 1; m >= 0; --m) {
-      run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, P.nreg[m], m, out_loglik);
+      run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, H.nact_post(m), m, out_loglik);
       if (m > 0)
         run.tuned(F_POST_REDUCE, MAP_GROUPED, "post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, nullptr,
-                  k_post_reduce, 0, P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+                  k_post_reduce, 0, H.nact_post(m - 1) * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);

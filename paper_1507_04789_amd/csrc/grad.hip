@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   const int th = blockIdx.y;
-  const int64_t i = tk0;
+  const int64_t i = P.act_post[P.act_post_off[m] + tk0];
   double* S = slice(P, th);
   Post po = post_of(P, S, m, i);
   Grad gr = grad_of(P, S, m, i);
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
   const int M = P.M;
   const int nkl = M * (M + 1) / 2;
   const int64_t gid = tk0;
-  const int64_t pidx = gid / nkl;
+  const int64_t pidx = P.act_post[P.act_post_off[M - 1] + gid / nkl];
   int l, k;
   kl_split((int)(gid % nkl), l, k);
   double* S = slice(P, th);
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double red[8];
   const int th = blockIdx.y;
-  const int64_t i = tk0;
+  const int64_t i = P.act_post[P.act_post_off[m] + tk0];
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
   Grad gr = grad_of(P, S, m, i);
@@ -481,16 +481,20 @@ __global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, TaskMap tm) {
   const int th = blockIdx.y;
   const int nkl = m * (m + 1) / 2;
   const int64_t gid = tk0;
-  const int64_t pidx = gid / nkl;
+  const int64_t pidx = P.act_post[P.act_post_off[m - 1] + gid / nkl];
   int l, k;
   kl_split((int)(gid % nkl), l, k);
   double* S = slice(P, th);
+  int64_t ch[8];       // children with observations below them
+  int nch = 0;
+  for (int c = 0; c < P.J; ++c)
+    if (post_active(P, m, pidx * P.J + c)) ch[nch++] = pidx * P.J + c;
   Acc acc;
   acc_zero(acc);
-  for (int cc = 0; cc < P.J; ++cc) acc_load(acc, grad_of(P, S, m, pidx * P.J + cc).Tsum(l, k), T, true);
-  gemm_segs(acc, P.J, [&](int cc) {
-    const int64_t ch = pidx * P.J + cc;
-    return seg<Op::T, Op::N>(grad_of(P, S, m, ch).Wbar(l), T, prior_reg(P, S, m, ch) + (int64_t)k * TT, T, 1.0);
+  for (int cc = 0; cc < nch; ++cc) acc_load(acc, grad_of(P, S, m, ch[cc]).Tsum(l, k), T, true);
+  gemm_segs(acc, nch, [&](int cc) {
+    return seg<Op::T, Op::N>(grad_of(P, S, m, ch[cc]).Wbar(l), T, prior_reg(P, S, m, ch[cc]) + (int64_t)k * TT, T,
+                             1.0);
   }, lds);
   acc_store(acc, grad_of(P, S, m - 1, pidx).Tsum(l, k), T);
 }
@@ -550,7 +554,8 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
-  for (int m = 0; m < M; ++m) run.tuned(F_RPOST, MAP_IDENTITY, "rpost", m, F.rpost[m], 1, nullptr, k_rpost, 0, P.nreg[m], m);
+  for (int m = 0; m < M; ++m)
+    run.tuned(F_RPOST, MAP_IDENTITY, "rpost", m, F.rpost[m], 1, nullptr, k_rpost, 0, H.nact_post(m), m);
   return hipGetLastError();
 }
 
@@ -569,12 +574,12 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, d
     run.tuned(F_RROWS, MAP_CHUNKED, "rrows_leaf", -1, F.rrows + F.rleaf_wbar, 1, H.cut_rrows, k_rrows_leaf, 0, nrow,
               theta);
     const int nkl = M * (M + 1) / 2;
-    run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, F.rT_leaf, nkl, nullptr, k_rT_leaf, 0, P.nreg[M - 1] * (int64_t)nkl);
+    run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, F.rT_leaf, nkl, nullptr, k_rT_leaf, 0, H.nact_post(M - 1) * (int64_t)nkl);
     for (int m = M - 1; m >= 0; --m) {
-      run.tuned(F_RPRIOR, MAP_IDENTITY, "rprior", m, F.rprior[m], 1, nullptr, k_rprior, 0, P.nreg[m], theta, m);
+      run.tuned(F_RPRIOR, MAP_IDENTITY, "rprior", m, F.rprior[m], 1, nullptr, k_rprior, 0, H.nact_post(m), theta, m);
       if (m > 0)
         run.tuned(F_RT, MAP_GROUPED, "rT", m, F.rT[m], m * (m + 1) / 2, nullptr, k_rT, 0,
-                  P.nreg[m - 1] * (int64_t)(m * (m + 1) / 2), m);
+                  H.nact_post(m - 1) * (int64_t)(m * (m + 1) / 2), m);
     }
   }
   hipLaunchKernelGGL(k_gsum, dim3(nth), dim3(NT), 0, st, P, theta, out_grad, nslot);

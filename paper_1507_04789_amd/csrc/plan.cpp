@@ -246,7 +246,46 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   }
   if (P->npad > INT32_MAX || P->ppad > INT32_MAX) return MRA_EINVAL;
 
-  // leaf-product order of the level-(M-1) regions
+  // pruning of regions with nothing below them
+  {
+    std::vector<int64_t> co(P->leaf_n.begin(), P->leaf_n.end()), cp(P->pleaf_n.begin(), P->pleaf_n.end());
+    std::vector<std::vector<int64_t>> obs_below(M), prd_below(M);
+    for (int m = M - 1; m >= 0; --m) {
+      obs_below[m].assign(P->nreg[m], 0);
+      prd_below[m].assign(P->nreg[m], 0);
+      for (int64_t i = 0; i < P->nreg[m]; ++i)
+        for (int c = 0; c < J; ++c) {
+          obs_below[m][i] += co[i * J + c];
+          prd_below[m][i] += cp[i * J + c];
+        }
+      co = obs_below[m];
+      cp = prd_below[m];
+    }
+    P->slot_prior.assign(n_internal, -1);
+    P->slot_post.assign(n_internal, -1);
+    P->act_prior.clear();
+    P->act_post.clear();
+    P->act_prior_off.assign(M + 1, 0);
+    P->act_post_off.assign(M + 1, 0);
+    for (int m = 0; m < M; ++m) {
+      P->act_prior_off[m] = (int64_t)P->act_prior.size();
+      P->act_post_off[m] = (int64_t)P->act_post.size();
+      for (int64_t i = 0; i < P->nreg[m]; ++i) {
+        if (obs_below[m][i] + prd_below[m][i] > 0) {
+          P->slot_prior[P->reg_base[m] + i] = (int32_t)(P->act_prior.size() - P->act_prior_off[m]);
+          P->act_prior.push_back((int32_t)i);
+        }
+        if (obs_below[m][i] > 0) {
+          P->slot_post[P->reg_base[m] + i] = (int32_t)(P->act_post.size() - P->act_post_off[m]);
+          P->act_post.push_back((int32_t)i);
+        }
+      }
+    }
+    P->act_prior_off[M] = (int64_t)P->act_prior.size();
+    P->act_post_off[M] = (int64_t)P->act_post.size();
+  }
+
+  // leaf-product order of the active level-(M-1) regions
   P->reduce_order.clear();
   for (int t = 0; t < 16; ++t) P->nsmall_thr[t] = 0;
   if (M > 0) {
@@ -257,12 +296,11 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
         const int64_t lf = q * J + c;
         maxnb[q] = std::max<int64_t>(maxnb[q], (P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T);
       }
-    P->reduce_order.resize(np);
-    std::iota(P->reduce_order.begin(), P->reduce_order.end(), 0);
+    P->reduce_order.assign(P->act_post.begin() + P->act_post_off[M - 1], P->act_post.begin() + P->act_post_off[M]);
     std::stable_sort(P->reduce_order.begin(), P->reduce_order.end(),
                      [&](int32_t x, int32_t y) { return maxnb[x] < maxnb[y]; });
     for (int t = 0; t < 16; ++t)
-      for (int64_t q = 0; q < np; ++q)
+      for (int32_t q : P->reduce_order)
         if (maxnb[q] < t) ++P->nsmall_thr[t];
   }
 
@@ -283,6 +321,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.g_trst = take(std::max<size_t>(P->trsm_tasks.size(), 1) * 4);
   L.g_lint = take(std::max<size_t>(P->linv_tasks.size(), 1) * 4);
   L.g_rord = take(std::max<size_t>(P->reduce_order.size(), 1) * 4);
+  L.g_slotp = take(std::max<size_t>(P->slot_prior.size(), 1) * 4);
+  L.g_slotq = take(std::max<size_t>(P->slot_post.size(), 1) * 4);
+  L.g_actp = take(std::max<size_t>(P->act_prior.size(), 1) * 4);
+  L.g_actq = take(std::max<size_t>(P->act_post.size(), 1) * 4);
   L.g_pxy = take(P->pred_xy.size() * 8);
   L.g_pgidx = take(P->pred_gidx.size() * 8);
   L.g_pt = take(std::max<size_t>(P->pred_tasks.size(), 1) * 4);
@@ -299,8 +341,13 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   D.n = n; D.npad = P->npad; D.n_leaves = n_leaves; D.ppad = P->ppad; D.n_pred = n_pred;
   int64_t w = 0;
   auto wtake = [&](int64_t doubles) { int64_t o = w; w = round_up(w + doubles, 32); return o; };
-  for (int m = 0; m <= M; ++m) { D.nreg[m] = P->nreg[m]; D.reg_base[m] = P->reg_base[m]; }
-  for (int m = 0; m < M; ++m) D.prior_off[m] = wtake(P->nreg[m] * (m + 2) * TT);
+  for (int m = 0; m <= M; ++m) {
+    D.nreg[m] = P->nreg[m];
+    D.reg_base[m] = P->reg_base[m];
+    D.act_prior_off[m] = P->act_prior_off[m];
+    D.act_post_off[m] = P->act_post_off[m];
+  }
+  for (int m = 0; m < M; ++m) D.prior_off[m] = wtake(P->nact_prior(m) * (m + 2) * TT);
   D.plane = P->npad * T;
   D.off_wobs = wtake((M + 1) * D.plane);
   D.off_sig = wtake(P->n_sig_tiles * TT);
@@ -313,7 +360,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
     // A tiles, omega, Ltilde, Ltilde^{-1}, Z tiles, z_omega, d, u
     D.post_stride[m] = round_up(nA * TT + (m + 1) * T + 2 * TT + m * TT + T + 2, 32);
-    D.post_off[m] = wtake(P->nreg[m] * D.post_stride[m]);
+    D.post_off[m] = wtake(P->nact_post(m) * D.post_stride[m]);
   }
   // reverse pass: per internal region G row tiles (m+1), omega-bar (T),
   // T-sums ((m+1)(m+2)/2 tiles), W-bar rows (m tiles) and W-bar^m (1 tile)
@@ -321,7 +368,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     for (int m = 0; m < M; ++m) {
       int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
       D.grad_stride[m] = round_up((m + 1) * TT + T + nA * TT + m * TT + TT, 32);
-      D.grad_off[m] = wtake(P->nreg[m] * D.grad_stride[m]);
+      D.grad_off[m] = wtake(P->nact_post(m) * D.grad_stride[m]);
     }
     D.off_v = wtake((M + 1) * D.plane);
     D.off_linv = wtake(P->n_sig_tiles * TT);
@@ -370,10 +417,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   F = PhaseFlops{};
   const double rr = r, Mr = M * rr;
   for (int m = 0; m < M; ++m) {
-    const double R = (double)P->nreg[m];
+    const double Rp = (double)P->nact_prior(m), R = (double)P->nact_post(m);   // active regions
     double pr = rr * rr * (m * rr) + rr * rr * rr / 3.0;                  // SYRK + POTRF
     for (int l = 0; l < m; ++l) pr += 2.0 * rr * rr * (l * rr) + rr * rr * rr;   // GEMM + TRSM
-    F.prior[m] = R * pr;
+    F.prior[m] = Rp * pr;
     const double k = m * rr + 1;
     F.post[m] = R * (rr * rr * rr / 3.0 + rr * rr * k);                        // POTRF + TRSM of [A^{m,<m} | w^m]
     // children of level m summed into level m-1: A~ = A - Z'Z per child

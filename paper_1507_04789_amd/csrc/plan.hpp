@@ -27,6 +27,7 @@ struct PhaseFlops {
 struct Layout {
   // geometry arena (byte offsets)
   size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst, g_lint, g_rord;
+  size_t g_slotp, g_slotq, g_actp, g_actq;
   size_t g_pxy, g_pgidx, g_pt, g_pleafn, g_ppoff, geom_bytes;
   // work arena (doubles per theta slice)
   int64_t theta_stride;
@@ -66,6 +67,16 @@ struct mra_plan_s {
   // the tile count from which a leaf is factored on the side stream (0: none)
   uint8_t tune[32] = {};
   int32_t big_tiles = 3;
+  // pruning: a region of level m < M is active for the posterior and the
+  // reverse pass when observations lie below it, and for the prior when
+  // observations or prediction points do; the others get no storage and no
+  // task.  slot_*[reg_base[m] + i] is the region's compact index within its
+  // level (-1 when pruned); act_* list the active regions level by level
+  // (act_*_off[m] .. act_*_off[m + 1]).
+  std::vector<int32_t> slot_prior, slot_post, act_prior, act_post;
+  std::vector<int64_t> act_prior_off, act_post_off;
+  int64_t nact_prior(int m) const { return act_prior_off[m + 1] - act_prior_off[m]; }
+  int64_t nact_post(int m) const { return act_post_off[m + 1] - act_post_off[m]; }
   // level-(M-1) regions ordered by their largest child's tile count
   // (ascending, tree order within); nsmall_thr[t] leads with children all
   // below t tiles, whose leaf products need none of the side stream's leaves

@@ -103,8 +103,18 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   // up the tree: eq. bfrecursion and the weight terms of eq. prediction
   for (int l = M - 1; l >= 0; --l) {
     const int64_t al = ancestor(P, M, leaf, l);
-    Post po = post_of(P, S, l, al);
     double* Bl = U + (int64_t)l * pplane;
+    if (!post_active(P, l, al)) {
+      // no observation below a_l: its posterior is its prior (Lt = I, Z = 0,
+      // z_w = 0), so Bh = B~^{l+1,l} and only the variance term remains
+      if (threadIdx.x < T) {
+        const double* b = Bl + threadIdx.x * T;
+        vv[threadIdx.x] += row_dot(b, b);
+      }
+      __syncthreads();
+      continue;
+    }
+    Post po = post_of(P, S, l, al);
     acc_zero(acc);
     gemm<Op::N, Op::T>(acc, Bl, T, po.Lti(), T, T, 1.0, lds);   // Bh = B~^{l+1,l} Lt^{-T}
     acc_store(acc, Bl, T);

@@ -128,3 +128,10 @@ def test_grad_batch_plain_fd_and_autograd():
     out = MRALogLik.apply(th, p, torch.tensor(w.z, device="cuda"))
     (out * torch.arange(1, 5, dtype=torch.float64, device="cuda")).sum().backward()
     np.testing.assert_array_equal(th.grad.numpy(), g * np.arange(1, 5)[:, None])
+
+
+def test_grad_swath_pruned_regions():
+    geom = wl.swath_geometry(5)
+    locs = wl.swath_locations(geom, 6000, 6)
+    z = np.random.default_rng(9).standard_normal(6000)
+    _case(locs, z, "matern32", _th(1.0, 0.08, 0.02), 6, 4, 9)

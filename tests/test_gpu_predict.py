@@ -67,3 +67,17 @@ def test_predict_one_dimensional_exact():
     z = g.standard_normal(300)
     pred = g.random((100, 1))
     _case(locs, z, pred, "exponential", _th(1.0, 0.3, 0.05), 5, 2, 1, d=1)
+
+
+def test_predict_swath_gaps_pruned_regions():
+    # satellite-swath scatter at a small size: most regions below level 2 hold
+    # no observation (pruned from the posterior) and the prediction points lie
+    # in the gaps (regions kept for the prior only)
+    geom = wl.swath_geometry(5)
+    locs = wl.swath_locations(geom, 6000, 6)
+    pred = wl.swath_locations(geom, 1500, 7, in_gaps=True)
+    z = np.random.default_rng(8).standard_normal(6000)
+    p = Plan(locs, M=6, J=4, r=9, cov="matern32", pred=pred)
+    leaves = np.diff(p.geometry()[1])
+    assert (leaves == 0).mean() > 0.5
+    _case(locs, z, pred, "matern32", _th(1.0, 0.08, 0.02), 6, 4, 9)
