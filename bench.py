@@ -253,6 +253,43 @@ def secondary_configs(dev, w2, theta_batch):
     return res
 
 
+def swath_config(dev):
+    """The satellite-swath workload at full size: n = 2^22 in 24 diagonal
+    strips of width 0.02 with three 10% gaps each, Matern nu = 1.5 with a
+    linear trend removed by the caller, M = 9, J = 4, r = 64 (73% of the
+    leaves empty, their regions pruned), kriging at 2^20 points in the gaps.
+    Graph replays; generation of the data takes about a minute on the host."""
+    import torch
+    from paper_1507_04789_amd import MRA_GRAPH, Plan
+    from paper_1507_04789_amd import workloads as wl
+    t0 = time.perf_counter()
+    w = wl.swaths()
+    z = w.z - (0.5 + w.locs[:, 0] - w.locs[:, 1])
+    gen_s = time.perf_counter() - t0
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, pred=w.pred, flags=MRA_GRAPH)
+    p.bind(dev)
+    zt = torch.tensor(z, device=dev)
+    th = torch.tensor(w.theta, device=dev).reshape(1, 3)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    mu = torch.empty(w.pred.shape[0], dtype=torch.float64, device=dev)
+    var = torch.empty_like(mu)
+    ms_g = _time_calls(lambda: p.loglik_grad(zt, th, out=(ll, g)), 3, warmup=1)
+    ms_l = _time_calls(lambda: p.loglik(zt, th, out=ll), 3, warmup=1)
+    ms_p = _time_calls(lambda: p.predict(zt, th, out=(mu, var)), 3, warmup=1)
+    res = {"workload": "swaths_n4194304_matern32_M9_J4_r64_pred1048576",
+           "work_arena_gb": p.work_bytes / 1e9, "generation_s": gen_s,
+           "loglik_grad_ms": ms_g, "loglik_grad_evals_per_s": 1000.0 / ms_g,
+           "loglik_grad_fp64_pct_peak": 100.0 * p.info["flops_grad"] / (ms_g * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
+           "loglik_ms": ms_l,
+           "loglik_fp64_pct_peak": 100.0 * p.info["flops_loglik"] / (ms_l * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
+           "predict_ms": ms_p, "n_pred": int(w.pred.shape[0]),
+           "loglik": float(ll[0]), "finite": bool(torch.isfinite(g).all() and torch.isfinite(mu).all())}
+    del p
+    torch.cuda.empty_cache()
+    return res
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -276,6 +313,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workloads (small uniform case, loglik only, 64-vector batch)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shapes (no autotuning)")
+    ap.add_argument("--swath", action="store_true",
+                    help="also run the n = 2^22 satellite-swath workload (about 250 GB of HBM, a minute of host time)")
     ap.add_argument("--theta-batch", type=int, default=16, help="parameter vectors per call in the 64-vector case")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
@@ -372,6 +411,8 @@ def main():
         del plan
         torch.cuda.empty_cache()
         secondary = secondary_configs(dev, w, args.theta_batch)
+        if args.swath:
+            secondary["swaths_n4194304"] = swath_config(dev)
 
     out = {
         "metric": METRIC,

@@ -67,3 +67,42 @@ def test_full_size_theta_batch(data):
         _check(float(ll[i]), g[i], pt)
     del p
     torch.cuda.empty_cache()
+
+
+def test_swath_full_size_properties():
+    """Satellite-swath workload at full size (n = 2^22 in 24 strips with
+    gaps, M = 9, r = 64, 73% of the leaves empty; 2^20 prediction points in
+    the gaps).  The oracle cannot run at this size, so the checks are
+    properties that hold at any size: the scale identity
+    loglik(s z; s^2 sigma^2, kappa, s^2 tau^2) = loglik(z; theta) - n log s,
+    mean(s z) = s mean(z) and var scaled by s^2, and the gradient against
+    central differences of the GPU log-likelihood."""
+    import math
+    torch.cuda.empty_cache()
+    w = wl.swaths()
+    z = w.z - (0.5 + w.locs[:, 0] - w.locs[:, 1])     # the caller removes the mean trend
+    print("full-size swath case: n=%d M=%d n_pred=%d" % (len(z), w.M, len(w.pred)), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, pred=w.pred, flags=0)
+    p.bind("cuda:0")
+    zt = torch.tensor(z, device="cuda:0")
+    th = torch.tensor(w.theta, dtype=torch.float64, device="cuda:0").reshape(1, 3)
+    ll, g = p.loglik_grad(zt, th)
+    ll, g = float(ll[0]), g[0].cpu().numpy()
+    assert math.isfinite(ll) and np.isfinite(g).all()
+    s = 2.0
+    shift = torch.tensor([[2 * math.log(s), 0.0, 2 * math.log(s)]], dtype=torch.float64, device="cuda:0")
+    l2 = float(p.loglik(zt * s, th + shift)[0])
+    assert abs(l2 - (ll - len(z) * math.log(s))) <= 1e-10 * abs(ll)
+    mu, var = p.predict(zt, th)
+    mu2, var2 = p.predict(zt * s, th + shift)
+    assert (var > 0).all()
+    assert float((mu2 - s * mu).abs().max()) <= 1e-10 * s * float(mu.abs().max())
+    assert float((var2 - s * s * var).abs().max()) <= 1e-10 * s * s * float(var.max())
+    h = 1e-4
+    for a in range(3):
+        e = torch.zeros(1, 3, dtype=torch.float64, device="cuda:0")
+        e[0, a] = h
+        fd = (float(p.loglik(zt, th + e)[0]) - float(p.loglik(zt, th - e)[0])) / (2 * h)
+        assert abs(fd - g[a]) <= 1e-5 * abs(g[a]) + 1e-3, (a, fd, g[a])
+    del p
+    torch.cuda.empty_cache()
