@@ -95,7 +95,7 @@ __global__ __launch_bounds__(NT) void k_sigma(DevPlan P, const double* theta, Ta
   Acc acc;
   acc_cov(acc, P.obs_xy + 2 * pi, nvi, P.obs_xy + 2 * pj, nvj, c, bi == bj, c.tau2);
   const double* W = S + P.off_wobs;
-  gemm_segs(acc, P.M,
+  gemm_segs2(acc, P.M,
             [&](int k) { return seg<Op::N, Op::T>(W + k * P.plane + pi * T, T, W + k * P.plane + pj * T, T, -1.0); },
             lds, round16(nvi), round16(nvj));
   acc_store(acc, S + P.off_sig + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT, T);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
   for (int ib = 0; ib < nb; ++ib) {
     const int mr = round16(min(T, nR - T * ib));
     acc_load(acc, X + (int64_t)ib * TT, T);
-    gemm_segs(acc, ib,
+    gemm_segs2(acc, ib,
               [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
               lds, mr);
     acc_store(acc, Y + (int64_t)ib * TT, T);
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
     const int64_t leaf = pidx * P.J + c;
     nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
-  gemm_segs(acc, nsg, [&](int sg) {
+  gemm_segs2(acc, nsg, [&](int sg) {
     int64_t leaf = pidx * P.J;
     int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
     while (sg >= nbl) {

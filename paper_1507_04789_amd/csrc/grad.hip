@@ -140,7 +140,7 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
 
 // ---------------------------------------------------------------- leaves
 // V = L_Sigma^{-T} Y for one column plane (backward substitution by tiles)
-__global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_v(DevPlan P, TaskMap tm) {
   for (int ib = nb - 1; ib >= 0; --ib) {
     const int mr = round16(min(T, nR - T * ib));
     acc_load(acc, Y + (int64_t)ib * TT, T);
-    gemm_segs(acc, nb - 1 - ib, [&](int q) {
+    gemm_segs2(acc, nb - 1 - ib, [&](int q) {
       const int jb = ib + 1 + q;
       return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
     }, lds, mr);
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, TaskMap tm) {
     Acc acc;
     acc_zero(acc);
     const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
-    gemm_segs(acc, M, [&](int k) { return seg_S(P, S, V + (int64_t)k * P.plane, k, c, M, leaf, 1.0); }, lds,
+    gemm_segs2(acc, M, [&](int k) { return seg_S(P, S, V + (int64_t)k * P.plane, k, c, M, leaf, 1.0); }, lds,
               round16(nx));
     const double* wb = wbar_omega_of(P, S, c, M, leaf);
 #pragma unroll
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   const int nvi = min(T, nR - T * bi), nvj = min(T, nR - T * bj);
   Acc acc;
   acc_zero(acc);
-  gemm_segs(acc, P.M + 1 + (nb - bi), [&](int q) {
+  gemm_segs2(acc, P.M + 1 + (nb - bi), [&](int q) {
     if (q <= P.M)
       return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0);
     const int kb = bi + q - (P.M + 1);
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
     const int64_t leaf = pidx * P.J + cc;
     nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
-  gemm_segs(acc, nsg, [&](int sg) {
+  gemm_segs2(acc, nsg, [&](int sg) {
     int64_t leaf = pidx * P.J;
     int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
     while (sg >= nbl) {

@@ -239,6 +239,108 @@ __device__ __forceinline__ void gemm_segs(Acc& acc, int nseg, F getseg, double* 
   }
 }
 
+// As gemm_segs, with two chunks in flight: the loads of chunk i + 2 are
+// issued while chunk i is multiplied, so each load has two chunk times to
+// arrive.  Costs one more register set (16 VGPRs); meant for kernels with
+// register headroom.
+template <class F>
+__device__ __forceinline__ void gemm_segs2(Acc& acc, int nseg, F getseg, double* lds, int mrows = T, int ncols = T) {
+  if (nseg <= 0) return;
+  const int w = wave_id(), l = lane_id();
+  const int ia = 32 * (w >> 1) + (l & 15);
+  const int jb = 32 * (w & 1) + (l & 15);
+  const int kr = l >> 4;
+  const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
+  const bool col0 = 32 * (w & 1) < ncols, col1 = 32 * (w & 1) + 16 < ncols;
+  int s = 0, cs = 0;
+  Seg cur = getseg(0);
+  auto advance = [&]() -> bool {
+    if (cs + 1 < cur.nch) {
+      ++cs;
+      return true;
+    }
+    if (s + 1 < nseg) {
+      ++s;
+      cs = 0;
+      cur = getseg(s);
+      return true;
+    }
+    return false;
+  };
+  auto compute = [&](const double* sA, double alpha_c) {
+    const double* sB = sA + KC * SLD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const double* ra = sA + (kk + kr) * SLD;
+      const double* rb = sB + (kk + kr) * SLD;
+      const double b0 = rb[jb], b1 = rb[jb + 16];
+      if (row0) {
+        const double a0 = alpha_c * ra[ia];
+        if (col0) acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+        if (col1) acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+      }
+      if (row1) {
+        const double a1 = alpha_c * ra[ia + 16];
+        if (col0) acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+        if (col1) acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+      }
+    }
+  };
+  // chunk 0 staged; chunks 1 and 2 in flight in register sets X and Y
+  {
+    const d4 va = fetch_rt(cur.A, cur.lda, 0, cur.ak);
+    const d4 vb = fetch_rt(cur.B, cur.ldb, 0, cur.bk);
+    stash_rt(lds, va, cur.ak);
+    stash_rt(lds + KC * SLD, vb, cur.bk);
+  }
+  double alpha_c = cur.alpha;
+  d4 xa = {0.0, 0.0, 0.0, 0.0}, xb = xa, ya = xa, yb = xa;
+  bool hx = advance(), hy = false;
+  bool fxa = cur.ak, fxb = cur.bk, fya = false, fyb = false;
+  double ax = cur.alpha, ay = 0.0;
+  if (hx) {
+    xa = fetch_rt(cur.A, cur.lda, cs * KC, cur.ak);
+    xb = fetch_rt(cur.B, cur.ldb, cs * KC, cur.bk);
+    hy = advance();
+    if (hy) {
+      fya = cur.ak, fyb = cur.bk, ay = cur.alpha;
+      ya = fetch_rt(cur.A, cur.lda, cs * KC, cur.ak);
+      yb = fetch_rt(cur.B, cur.ldb, cs * KC, cur.bk);
+    }
+  }
+  __syncthreads();
+  int stage = 0;
+  for (;;) {
+    compute(lds + stage * 2 * KC * SLD, alpha_c);
+    if (!hx) break;
+    stage ^= 1;
+    stash_rt(lds + stage * 2 * KC * SLD, xa, fxa);
+    stash_rt(lds + stage * 2 * KC * SLD + KC * SLD, xb, fxb);
+    alpha_c = ax;
+    hx = hy && advance();
+    if (hx) {
+      fxa = cur.ak, fxb = cur.bk, ax = cur.alpha;
+      xa = fetch_rt(cur.A, cur.lda, cs * KC, cur.ak);
+      xb = fetch_rt(cur.B, cur.ldb, cs * KC, cur.bk);
+    }
+    __syncthreads();
+    compute(lds + stage * 2 * KC * SLD, alpha_c);
+    if (!hy) break;
+    stage ^= 1;
+    stash_rt(lds + stage * 2 * KC * SLD, ya, fya);
+    stash_rt(lds + stage * 2 * KC * SLD + KC * SLD, yb, fyb);
+    alpha_c = ay;
+    hy = hx && advance();
+    if (hy) {
+      fya = cur.ak, fyb = cur.bk, ay = cur.alpha;
+      ya = fetch_rt(cur.A, cur.lda, cs * KC, cur.ak);
+      yb = fetch_rt(cur.B, cur.ldb, cs * KC, cur.bk);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
 // Seg for one 64x64x64 block product in the gemm<> operand conventions
 template <Op OA, Op OB>
 __device__ __forceinline__ Seg seg(const double* A, int lda, const double* B, int ldb, double alpha, int nch = T / KC) {
