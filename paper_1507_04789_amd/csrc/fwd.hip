@@ -54,7 +54,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
   row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds);
   Acc acc;
   acc_cov(acc, X, P.r, X, P.r, c, true, 0.0);
-  gemm_segs(acc, m, [&](int k) { return seg<Op::N, Op::T>(reg + k * TT, T, reg + k * TT, T, -1.0); }, lds,
+  gemm_segs2(acc, m, [&](int k) { return seg<Op::N, Op::T>(reg + k * TT, T, reg + k * TT, T, -1.0); }, lds,
             round16(P.r));
   acc_to_lds(acc, lds);
   __syncthreads();
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
     double* Dj = base + ((int64_t)jb * nb + jb) * TT;
     const double* Lj = base + (int64_t)jb * nb * TT;   // row jb of tiles
     acc_load(acc, Dj, T);
-    gemm_segs(acc, jb, [&](int k) { return seg<Op::N, Op::T>(Lj + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); },
+    gemm_segs2(acc, jb, [&](int k) { return seg<Op::N, Op::T>(Lj + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); },
               lds);
     acc_to_lds(acc, lds);
     __syncthreads();
@@ -138,12 +138,12 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
       double* X = base + ((int64_t)ib * nb + jb) * TT;
       const double* Li = base + (int64_t)ib * nb * TT;
       acc_load(acc, X, T);
-      gemm_segs(acc, jb,
+      gemm_segs2(acc, jb,
                 [&](int k) { return seg<Op::N, Op::T>(Li + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); }, lds);
       acc_store(acc, X, T);
       __syncthreads();
       acc_zero(acc);
-      gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
+      gemm_segs2(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
       acc_store(acc, X, T);
       __syncthreads();
     }
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
 
 // child sums for level m-1 (eq. mainquantities with eq. helpquantities):
 //   A^{k,l}_P = sum_c (A^{k,l}_c - Z^k_c' Z^l_c),  w^k_P = sum_c (w^k_c - Z^k_c' z_c)
-__global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_post_reduce(DevPlan P, int m, TaskMap tm
   Acc acc;
   acc_zero(acc);
   for (int c = 0; c < nch; ++c) acc_load(acc, post_of(P, S, m, ch[c]).A(k, l), T, true);
-  gemm_segs(acc, nch, [&](int c) {
+  gemm_segs2(acc, nch, [&](int c) {
     Post pc = post_of(P, S, m, ch[c]);
     return seg<Op::T, Op::N>(pc.Z(k), T, pc.Z(l), T, -1.0);
   }, lds);

@@ -474,7 +474,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
 
 // Tsum of a level-(m-1) region: sum over children (level m) of
 // Tsum_c^{l,k} + Wbar_c^l' W^^k_c, k <= l <= m-1
-__global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 3) void k_rT(DevPlan P, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_rT(DevPlan P, int m, TaskMap tm) {
   Acc acc;
   acc_zero(acc);
   for (int cc = 0; cc < nch; ++cc) acc_load(acc, grad_of(P, S, m, ch[cc]).Tsum(l, k), T, true);
-  gemm_segs(acc, nch, [&](int cc) {
+  gemm_segs2(acc, nch, [&](int cc) {
     return seg<Op::T, Op::N>(grad_of(P, S, m, ch[cc]).Wbar(l), T, prior_reg(P, S, m, ch[cc]) + (int64_t)k * TT, T,
                              1.0);
   }, lds);
