@@ -64,7 +64,7 @@ __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const doub
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
     acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
-    gemm_segs(acc, l, [&](int k) { return seg<Op::N, Op::T>(rows + k * bstride, T, Pa + k * TT, T, -1.0); }, lds,
+    gemm_segs2(acc, l, [&](int k) { return seg<Op::N, Op::T>(rows + k * bstride, T, Pa + k * TT, T, -1.0); }, lds,
               mrows);
     double* out = rows + l * bstride;
     acc_store(acc, out, T);

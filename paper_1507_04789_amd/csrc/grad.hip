@@ -316,7 +316,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
     const double* Pa = prior_reg(P, S, l, al);
     double* Rl = rows + l * bstride;
     init(acc, l);
-    gemm_segs(acc, nextra + lev - 1 - l, [&](int q) {
+    gemm_segs2(acc, nextra + lev - 1 - l, [&](int q) {
       if (q < nextra) return extra(l, q);
       const int lp = l + 1 + (q - nextra);
       return seg<Op::N, Op::N>(rows + lp * bstride, T, prior_reg(P, S, lp, ancestor(P, lev, idx, lp)) + (int64_t)l * TT,
