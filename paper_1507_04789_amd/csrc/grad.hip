@@ -322,10 +322,11 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
       return seg<Op::N, Op::N>(rows + lp * bstride, T, prior_reg(P, S, lp, ancestor(P, lev, idx, lp)) + (int64_t)l * TT,
                                T, -1.0);
     }, lds, mr);
-    acc_store(acc, Rl, T);
+    // W-bar^l = W^-bar^l L^{-1}: the left factor stays in LDS
+    acc_to_lds(acc, lds);
     __syncthreads();
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(Rl, T, Pa + (l + 1) * TT, T, 1.0); }, lds, mr);
+    gemm_lds_a(acc, lds, Pa + (l + 1) * TT, T, 1.0, lds + LDS_DOUBLES, mr);
     acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
     acc_store(acc, Rl, T);
     __syncthreads();
@@ -337,7 +338,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
 __global__ __launch_bounds__(NT, 3) void k_rrows_leaf(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   __shared__ double red[8];
   const int th = blockIdx.y;
   const int64_t tk = tk0;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
 __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   __shared__ double red[8];
   const int th = blockIdx.y;
   const int64_t i = P.act_post[P.act_post_off[m] + tk0];

@@ -25,6 +25,7 @@ constexpr int KC = 16;        // k-chunk staged in LDS
 constexpr int SLD = T + 4;    // LDS row pitch of a staged chunk (doubles)
 constexpr int PLD = T + 1;    // LDS row pitch of a factorisation tile
 constexpr int LDS_DOUBLES = 4 * KC * SLD;   // two stages of A and B chunks
+constexpr int LDS_SWEEP = LDS_DOUBLES + 2 * KC * SLD;   // plus two B-only stages (gemm_lds_a)
 static_assert(LDS_DOUBLES >= T * PLD, "the LDS buffer also holds one factorisation tile");
 
 struct Acc {
@@ -339,6 +340,47 @@ __device__ __forceinline__ void gemm_segs2(Acc& acc, int nseg, F getseg, double*
     __syncthreads();
   }
   __syncthreads();
+}
+
+// acc += alpha * A * B for one 64x64x64 product whose A operand is already
+// in LDS (row-major, pitch PLD, as acc_to_lds leaves it) and whose B operand
+// is k-major in global memory (B(k, j) = B[k * ldb + j]); only B streams,
+// through `stage` (2 * KC * SLD doubles, disjoint from A).  Output row
+// blocks at or beyond mrows are not multiplied.
+__device__ __forceinline__ void gemm_lds_a(Acc& acc, const double* A, const double* B, int ldb, double alpha,
+                                           double* stage, int mrows = T) {
+  const int w = wave_id(), l = lane_id();
+  const int ia = 32 * (w >> 1) + (l & 15);
+  const int jb = 32 * (w & 1) + (l & 15);
+  const int kr = l >> 4;
+  const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
+  d4 vb = fetch_rt(B, ldb, 0, true);
+  stash_rt(stage, vb, true);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < T / KC; ++c) {
+    const bool more = c + 1 < T / KC;
+    if (more) vb = fetch_rt(B, ldb, (c + 1) * KC, true);
+    const double* sB = stage + (c & 1) * KC * SLD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int k = c * KC + kk + kr;
+      const double* rb = sB + (kk + kr) * SLD;
+      const double b0 = rb[jb], b1 = rb[jb + 16];
+      if (row0) {
+        const double a0 = alpha * A[ia * PLD + k];
+        acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+      }
+      if (row1) {
+        const double a1 = alpha * A[(ia + 16) * PLD + k];
+        acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+      }
+    }
+    if (more) stash_rt(stage + ((c + 1) & 1) * KC * SLD, vb, true);
+    __syncthreads();
+  }
 }
 
 // Seg for one 64x64x64 block product in the gemm<> operand conventions
