@@ -56,8 +56,9 @@ __device__ __forceinline__ void record_failure(const DevPlan& P, double* S, int 
 
 // Row sweep of eq. priorw for 64 rows (points X, nx valid) of a region at
 // level `lev` with index `idx`: writes W^^l (l < lev) to rows + l*bstride.
+// lds holds LDS_DOUBLES doubles, stage 2 * KC * SLD more (disjoint).
 __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const double* X, int nx, double* rows,
-                          int64_t bstride, int lev, int64_t idx, double* lds) {
+                          int64_t bstride, int lev, int64_t idx, double* lds, double* stage) {
   Acc acc;
   const int mrows = round16(nx);
   for (int l = 0; l < lev; ++l) {
@@ -67,11 +68,12 @@ __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const doub
     gemm_segs2(acc, l, [&](int k) { return seg<Op::N, Op::T>(rows + k * bstride, T, Pa + k * TT, T, -1.0); }, lds,
               mrows);
     double* out = rows + l * bstride;
-    acc_store(acc, out, T);
+    // W^^l = W^l L_{a_l}^{-T}: W^l stays in LDS, L^{-1} streams through `stage`
+    acc_to_lds(acc, lds);
     __syncthreads();
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::T>(out, T, Pa + (l + 1) * TT, T, 1.0); }, lds, mrows);
-    acc_store(acc, out, T);   // W^l L_{a_l}^{-T}
+    gemm_lds_a(acc, lds, Pa + (l + 1) * TT, T, false, 1.0, stage, mrows);
+    acc_store(acc, out, T);
     __syncthreads();
   }
 }

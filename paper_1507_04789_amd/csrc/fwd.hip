@@ -51,7 +51,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
   const CovP c = load_cov(theta + 3 * th, P.cov);
   double* reg = prior_reg(P, S, m, i);
   const double* X = knots_of(P, m, i);
-  row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds);
+  row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds, lds_x);   // lds_x is free until the factorisation
   Acc acc;
   acc_cov(acc, X, P.r, X, P.r, c, true, 0.0);
   gemm_segs2(acc, m, [&](int k) { return seg<Op::N, Op::T>(reg + k * TT, T, reg + k * TT, T, -1.0); }, lds,
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
 __global__ __launch_bounds__(NT, 2) void k_leaf_rows(DevPlan P, const double* theta, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   const int th = blockIdx.y;
   const int32_t* task = P.row_tasks + 2 * tk0;
   const int leaf = task[0];
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_rows(DevPlan P, const double* th
   double* S = slice(P, th);
   const CovP c = load_cov(theta + 3 * th, P.cov);
   const int nx = min(T, (int)(P.leaf_n[leaf] - (p0 - P.leaf_poff[leaf])));
-  row_sweep(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wobs + p0 * T, P.plane, P.M, leaf, lds);
+  row_sweep(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wobs + p0 * T, P.plane, P.M, leaf, lds, lds + LDS_DOUBLES);
 }
 
 // Sigma_R = C_0(S_R, S_R) + tau^2 I - W^_R W^_R' per tile (bi >= bj)

@@ -326,7 +326,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
     acc_to_lds(acc, lds);
     __syncthreads();
     acc_zero(acc);
-    gemm_lds_a(acc, lds, Pa + (l + 1) * TT, T, 1.0, lds + LDS_DOUBLES, mr);
+    gemm_lds_a(acc, lds, Pa + (l + 1) * TT, T, true, 1.0, lds + LDS_DOUBLES, mr);
     acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
     acc_store(acc, Rl, T);
     __syncthreads();

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
                                                 TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   __shared__ double mu[T], vv[T];
   const int64_t tk = tk0;
   const int32_t* task = P.pred_tasks + 2 * tk;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   const int nx = min(T, (int)(P.pleaf_n[leaf] - (q0 - P.pleaf_poff[leaf])));
   double* U = S + P.off_pw + q0 * T;      // plane l at U + l * ppad * T
   const int64_t pplane = P.ppad * T;
-  row_sweep(P, S, c, X, nx, U, pplane, M, leaf, lds);
+  row_sweep(P, S, c, X, nx, U, pplane, M, leaf, lds, lds + LDS_DOUBLES);
   // leaf quantities
   const int64_t poff = P.leaf_poff[leaf];
   const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);

@@ -344,23 +344,24 @@ __device__ __forceinline__ void gemm_segs2(Acc& acc, int nseg, F getseg, double*
 
 // acc += alpha * A * B for one 64x64x64 product whose A operand is already
 // in LDS (row-major, pitch PLD, as acc_to_lds leaves it) and whose B operand
-// is k-major in global memory (B(k, j) = B[k * ldb + j]); only B streams,
-// through `stage` (2 * KC * SLD doubles, disjoint from A).  Output row
-// blocks at or beyond mrows are not multiplied.
-__device__ __forceinline__ void gemm_lds_a(Acc& acc, const double* A, const double* B, int ldb, double alpha,
-                                           double* stage, int mrows = T) {
+// is in global memory, k-major (B(k, j) = B[k * ldb + j]) when bk, else
+// B(k, j) = B[j * ldb + k]; only B streams, through `stage` (2 * KC * SLD
+// doubles, disjoint from A).  Output row blocks at or beyond mrows are not
+// multiplied.
+__device__ __forceinline__ void gemm_lds_a(Acc& acc, const double* A, const double* B, int ldb, bool bk,
+                                           double alpha, double* stage, int mrows = T) {
   const int w = wave_id(), l = lane_id();
   const int ia = 32 * (w >> 1) + (l & 15);
   const int jb = 32 * (w & 1) + (l & 15);
   const int kr = l >> 4;
   const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
-  d4 vb = fetch_rt(B, ldb, 0, true);
-  stash_rt(stage, vb, true);
+  d4 vb = fetch_rt(B, ldb, 0, bk);
+  stash_rt(stage, vb, bk);
   __syncthreads();
 #pragma unroll 1
   for (int c = 0; c < T / KC; ++c) {
     const bool more = c + 1 < T / KC;
-    if (more) vb = fetch_rt(B, ldb, (c + 1) * KC, true);
+    if (more) vb = fetch_rt(B, ldb, (c + 1) * KC, bk);
     const double* sB = stage + (c & 1) * KC * SLD;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
@@ -378,7 +379,7 @@ __device__ __forceinline__ void gemm_lds_a(Acc& acc, const double* A, const doub
         acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
       }
     }
-    if (more) stash_rt(stage + ((c + 1) & 1) * KC * SLD, vb, true);
+    if (more) stash_rt(stage + ((c + 1) & 1) * KC * SLD, vb, bk);
     __syncthreads();
   }
 }
