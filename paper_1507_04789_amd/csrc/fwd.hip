@@ -283,15 +283,16 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   const double ld = 2.0 * logdiag_lds(lds, T, red);
   lds_to_global(lds, po.Lt());
   __syncthreads();
+  // Z_l = Lt^{-1} A^{m,l}: the inverse is still in lds_x (pitch PLD)
   Acc acc;
   for (int l = 0; l < m; ++l) {
     acc_zero(acc);
-    gemm<Op::N, Op::N>(acc, po.Lti(), T, po.A(m, l), T, T, 1.0, lds);
+    gemm_lds_a(acc, lds_x, po.A(m, l), T, true, 1.0, lds);
     acc_store(acc, po.Z(l), T);
   }
   double zq = 0.0;
   if (threadIdx.x < T) {
-    const double* Li = po.Lti() + threadIdx.x * T;
+    const double* Li = lds_x + threadIdx.x * PLD;
     const double* w = po.omega(m);
     for (int q = 0; q <= (int)threadIdx.x; ++q) zq += Li[q] * w[q];
     po.zw()[threadIdx.x] = zq;
