@@ -144,17 +144,20 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   const Side sd = side_of(H);
   const Side* side = overlap ? &sd : nullptr;
   if ((e = launch_forward_front(*H, y, theta, nth, st, side)) != hipSuccess) return e;
-  if (side) {
+  const bool on_side = side && H->side_solves;
+  if (on_side) {
     // leaf solves on the side stream, after the small leaves (fork2) and,
     // in stream order, after the large ones
     if ((e = hipEventRecord(sd.fork2, st)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(sd.s, sd.fork2, 0)) != hipSuccess) return e;
+  } else if (side && H->nbig() > 0) {
+    if ((e = hipStreamWaitEvent(st, sd.big, 0)) != hipSuccess) return e;   // they need every leaf
   }
-  if ((e = launch_grad_leafsolve(*H, nth, side ? sd.s : st)) != hipSuccess) return e;
-  if (side && (e = hipEventRecord(sd.join, sd.s)) != hipSuccess) return e;
+  if ((e = launch_grad_leafsolve(*H, nth, on_side ? sd.s : st)) != hipSuccess) return e;
+  if (on_side && (e = hipEventRecord(sd.join, sd.s)) != hipSuccess) return e;
   if ((e = launch_forward_back(*H, nth, ll, st, side)) != hipSuccess) return e;
   if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
-  if (side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
+  if (on_side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
   return launch_grad_rest(*H, theta, nth, g, st);
 }
 
@@ -166,7 +169,8 @@ std::string tuning_json(const mra_plan_s* H, double ms) {
     std::snprintf(buf, sizeof buf, "\"ms_per_call\": %.6g, ", ms);
     j += buf;
   }
-  std::snprintf(buf, sizeof buf, "\"big_leaf_tiles\": %d, \"families\": {", H->big_tiles);
+  std::snprintf(buf, sizeof buf, "\"big_leaf_tiles\": %d, \"side_solves\": %d, \"families\": {", H->big_tiles,
+                H->side_solves);
   j += buf;
   for (int f = 0; f < F_COUNT; ++f) {
     std::snprintf(buf, sizeof buf, "%s\"%s\": \"%s\"", f ? ", " : "", fam_name(f), map_name(H->tune[f]));
@@ -425,8 +429,14 @@ mra_status mra_set_tuning(mra_plan_t P, const char* json) {
     big = std::atoi(v.c_str());
     if (big < 0 || big > 64) return MRA_EINVAL;
   }
+  int32_t sides = P->side_solves;
+  if (json_value(json, "side_solves", v)) {
+    sides = std::atoi(v.c_str());
+    if (sides != 0 && sides != 1) return MRA_EINVAL;
+  }
   std::memcpy(P->tune, t, sizeof t);
   P->big_tiles = big;
+  P->side_solves = sides;
   if (P->graphs) P->graphs->clear();
   return MRA_OK;
 }
@@ -501,6 +511,15 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
       }
     }
     P->big_tiles = pick;
+    if (grad) {
+      const int32_t keep_s = P->side_solves;
+      P->side_solves = 1 - keep_s;
+      const double t = measure();
+      if (t < best * 0.995)
+        best = t;
+      else
+        P->side_solves = keep_s;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -67,6 +67,7 @@ struct mra_plan_s {
   // the tile count from which a leaf is factored on the side stream (0: none)
   uint8_t tune[32] = {};
   int32_t big_tiles = 3;
+  int32_t side_solves = 1;   // reverse-pass leaf solves on the side stream (1) or the main stream (0)
   // pruning: a region of level m < M is active for the posterior and the
   // reverse pass when observations lie below it, and for the prior when
   // observations or prediction points do; the others get no storage and no
