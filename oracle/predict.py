@@ -84,3 +84,20 @@ def predict(geom: Geometry, z, cov_kind, theta, pred):
         mean[ip] = mu
         var[ip] = vv
     return mean, var
+
+
+def data_gradient(geom: Geometry, z, cov_kind, theta, idx=None):
+    """d loglik / d z = -Sigma^{-1} z at the observations idx (all when None).
+
+    Sigma = C_M(S, S) + tau^2 I is the M-RA data covariance (measurement
+    error as in Sec. 4.2), and C_M(S, S) is the covariance of the latent
+    y_M at S.  The posterior mean of Prop. 2 at the observed locations is
+    therefore E[y_M(S) | z] = C_M(S, S) Sigma^{-1} z = z - tau^2 Sigma^{-1} z,
+    so -Sigma^{-1} z = (E[y_M(S) | z] - z) / tau^2: the gradient is the
+    scaled residual of the kriging pass (Sec. 3.4) run at S itself.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    idx = np.arange(z.shape[0]) if idx is None else np.asarray(idx, dtype=np.int64)
+    cov = Covariance(cov_kind, theta)
+    mean, _ = predict(geom, z, cov_kind, theta, geom.locs[idx])
+    return (mean - z[idx]) / cov.tau2

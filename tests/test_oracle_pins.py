@@ -294,3 +294,48 @@ def test_covariance_closed_forms():
         cp = Covariance(kind, th + np.array([0, h, 0]))(X, Y)[0, 0]
         cm = Covariance(kind, th - np.array([0, h, 0]))(X, Y)[0, 0]
         assert abs(cov.tangents(X, Y)[1, 0, 0] - (cp - cm) / (2 * h)) <= 1e-8
+
+
+# Data gradient d loglik / d z = -Sigma^{-1} z (computed by the oracle from
+# the kriging residual at the observed locations, Prop. 2) against the dense
+# brute-force Sigma of the Sec. 2.4 closed form: independent of the prior,
+# posterior and prediction recursions
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("M,r", [(0, 4), (1, 9), (2, 4), (3, 4)])
+def test_data_gradient_matches_dense(kind, M, r):
+    locs, z = _data(150, seed=11)
+    th = _theta(t2=0.08)
+    g = Geometry(locs, 2, M, 4, r)
+    gz = predict.data_gradient(g, z, kind, th)
+    V, _ = dense.data_covariance(g, Covariance(kind, th))
+    ref = -np.linalg.solve(V, z)
+    np.testing.assert_allclose(gz, ref, rtol=1e-8, atol=1e-9 * np.abs(ref).max())
+    # a subset of the observations gives the same entries
+    idx = np.array([3, 77, 149, 0])
+    np.testing.assert_allclose(predict.data_gradient(g, z, kind, th, idx), gz[idx], rtol=1e-12, atol=0)
+
+
+# The log-likelihood is quadratic in z, so a central difference with any
+# step is exact: loglik(z + v) - loglik(z - v) = 2 v' (d loglik / d z).
+# Ties the kriging-residual gradient to the likelihood recursion itself.
+@pytest.mark.parametrize("kind", COVS)
+def test_data_gradient_exact_central_difference(kind):
+    locs, z = _data(200, seed=12)
+    th = _theta(k=0.15, t2=0.03)
+    g = Geometry(locs, 2, 3, 4, 9)
+    gz = predict.data_gradient(g, z, kind, th)
+    v = np.random.default_rng(5).standard_normal(z.shape[0])
+    lp, _, _ = mra.loglik(g, z + v, kind, th)
+    lm, _, _ = mra.loglik(g, z - v, kind, th)
+    assert abs((lp - lm) - 2 * v @ gz) <= 1e-9 * (abs(lp) + abs(lm))
+
+
+# M = 0: the textbook Gaussian -(C_0 + tau^2 I)^{-1} z
+def test_data_gradient_m0_textbook():
+    locs, z = _data(120, seed=13)
+    th = _theta()
+    g = Geometry(locs, 2, 0, 4, 16)
+    cov = Covariance("matern32", th)
+    ref = -np.linalg.solve(cov(locs, locs) + cov.tau2 * np.eye(120), z)
+    np.testing.assert_allclose(predict.data_gradient(g, z, "matern32", th), ref, rtol=1e-9,
+                               atol=1e-10 * np.abs(ref).max())
