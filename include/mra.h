@@ -153,6 +153,19 @@ mra_status mra_loglik_grad(mra_plan_t plan, const double* d_y, const double* d_t
                            int32_t n_theta, double* d_loglik, double* d_grad, void* stream);
 
 /*
+ * As mra_loglik_grad, plus the gradient with respect to the data,
+ * d_grad_y[n_theta][n] = d loglik / d z = -Sigma(theta)^{-1} z (caller's
+ * order; Sigma as for mra_loglik).  It is the z column of the leaves'
+ * bordered-step cotangent in the same reverse pass, so it adds no pass of
+ * its own.  All outputs are required, in caller-owned device memory that
+ * does not overlap d_y.  MRA_EINVAL for a NULL pointer, MRA_ESTATE for a
+ * plan built with MRA_NO_GRAD.
+ */
+mra_status mra_loglik_grad_data(mra_plan_t plan, const double* d_y, const double* d_theta,
+                                int32_t n_theta, double* d_loglik, double* d_grad,
+                                double* d_grad_y, void* stream);
+
+/*
  * Posterior predictive mean and variance of the latent process y_M at the
  * plan's prediction locations (Prop. 2, marginal variances), for one
  * parameter vector d_theta[3].  d_mean[n_pred], d_var[n_pred] in the

@@ -168,6 +168,50 @@ class Plan:
         self._fail(s, "mra_loglik_grad")
         return out, g
 
+    def loglik_grad_data(self, y, theta, out=None):
+        """(loglik [n_theta], grad [n_theta, 3], grad_y [n_theta, n]), where
+        grad_y = d loglik / d y = -Sigma^{-1} y in the caller's order, from
+        the same reverse pass; out = (loglik, grad, grad_y) optionally names
+        the output tensors."""
+        y, theta = self._prep(y, theta)
+        out, g, gy = (None, None, None) if out is None else out
+        out = self._out(out, (theta.shape[0],))
+        g = self._out(g, (theta.shape[0], 3))
+        gy = self._out(gy, (theta.shape[0], self.n))
+        s = _lib.lib().mra_loglik_grad_data(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
+                                            g.data_ptr(), gy.data_ptr(), self._stream())
+        self._fail(s, "mra_loglik_grad_data")
+        return out, g, gy
+
+    def fit(self, y, theta0, *, batch: int | None = None, **kw):
+        """Maximum-likelihood estimate of (log sigma^2, log kappa, log tau^2)
+        from theta0 by L-BFGS with a batched line search (mle.maximize):
+        each iteration evaluates `batch` step lengths (default max_theta, at
+        most 8) in one loglik_grad call.  Keyword arguments go to
+        mle.maximize; returns its FitResult."""
+        from . import mle
+        torch = _torch()
+        k = min(self.max_theta, 8) if batch is None else int(batch)
+        if not 1 <= k <= self.max_theta:
+            raise ValueError("batch must lie in 1..max_theta (%d)" % self.max_theta)
+        y, _ = self._prep(y, np.zeros(3))
+        bufs = {}
+
+        def evaluate(th):
+            m = th.shape[0]
+            if m not in bufs:
+                bufs[m] = tuple(torch.empty(s, dtype=torch.float64, device=self.device) for s in ((m, 3), (m,), (m, 3)))
+            tb, lb, gb = bufs[m]
+            tb.copy_(torch.from_numpy(np.ascontiguousarray(th, dtype=np.float64)))
+            try:
+                self.loglik_grad(y, tb, out=(lb, gb))
+            except MRAError as e:   # a failed factorisation leaves NaN in its entries only
+                if e.status != _lib.MRA_ENOTPD:
+                    raise
+            return lb.cpu().numpy(), gb.cpu().numpy()
+
+        return mle.maximize(evaluate, theta0, batch=k, **kw)
+
     def predict(self, y, theta, out=None):
         """Posterior predictive (mean, var) of the latent process at the
         plan's prediction locations, for one parameter vector; out =
@@ -229,8 +273,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.mra_destroy(h)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None   # None at interpreter shutdown
+        if h is not None and L is not None:
+            L.mra_destroy(h)
             self._h = None
 
 
@@ -240,20 +285,27 @@ def _make_autograd():
     class MRALogLik(torch.autograd.Function):
         """loglik(theta) with the library's reverse-pass gradient.
 
-        forward(theta [n_theta, 3], plan, y) -> loglik [n_theta]; the
-        gradient with respect to y is not provided."""
+        forward(theta [n_theta, 3], plan, y) -> loglik [n_theta]; when y
+        requires grad, its gradient comes from the same reverse pass."""
 
         @staticmethod
         def forward(ctx, theta, plan, y):
-            ll, g = plan.loglik_grad(y, theta.detach())
-            ctx.save_for_backward(g)
+            if ctx.needs_input_grad[2]:
+                ll, g, gy = plan.loglik_grad_data(y.detach(), theta.detach())
+            else:
+                (ll, g), gy = plan.loglik_grad(y, theta.detach()), None
+            ctx.save_for_backward(g, gy)
             ctx.theta_device = theta.device
+            ctx.y_device = y.device
             return ll
 
         @staticmethod
         def backward(ctx, gout):
-            (g,) = ctx.saved_tensors
-            return (gout.to(g.device)[:, None] * g).to(ctx.theta_device), None, None
+            g, gy = ctx.saved_tensors
+            go = gout.to(g.device)
+            dtheta = (go[:, None] * g).to(ctx.theta_device)
+            dy = None if gy is None else (go @ gy).to(ctx.y_device)
+            return dtheta, None, dy
 
     return MRALogLik
 

@@ -137,7 +137,7 @@ hipError_t run_call(mra_plan_s* H, const GraphKey& key, hipStream_t st, F enqueu
 }
 
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
-                           hipStream_t st) {
+                           double* gy, hipStream_t st) {
   const bool overlap = !(H->cfg.flags & MRA_PLAIN);
   hipError_t e;
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
@@ -158,7 +158,7 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   if ((e = launch_forward_back(*H, nth, ll, st, side)) != hipSuccess) return e;
   if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
   if (on_side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
-  return launch_grad_rest(*H, theta, nth, g, st);
+  return launch_grad_rest(*H, theta, nth, g, gy, st);
 }
 
 // ---- tuning table (JSON) ----
@@ -358,8 +358,9 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   return MRA_OK;
 }
 
-mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
-                           double* d_grad, void* stream) {
+namespace {
+mra_status loglik_grad_call(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta,
+                            double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
   mra_status s = check_call(P, n_theta);
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
@@ -367,13 +368,25 @@ mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_thet
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
   if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
-  const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, nullptr}};
+  const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, d_grad_y}};
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
-    return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, q);
+    return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, q);
   }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
   return MRA_OK;
+}
+}  // namespace
+
+mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
+                           double* d_grad, void* stream) {
+  return loglik_grad_call(P, d_y, d_theta, n_theta, d_loglik, d_grad, nullptr, stream);
+}
+
+mra_status mra_loglik_grad_data(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta,
+                                double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
+  if (!d_grad_y) return MRA_EINVAL;
+  return loglik_grad_call(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, stream);
 }
 
 mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_var,
@@ -455,7 +468,7 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
   P->last_nth = n_theta;
   const Side sd = side_of(P);
   auto call = [&]() -> hipError_t {
-    if (grad) return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, st);
+    if (grad) return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, nullptr, st);
     hipError_t e = launch_forward_front(*P, d_y, d_theta, n_theta, st, overlap ? &sd : nullptr);
     return e != hipSuccess ? e : launch_forward_back(*P, n_theta, d_loglik, st, overlap ? &sd : nullptr);
   };

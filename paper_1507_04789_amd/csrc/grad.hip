@@ -208,7 +208,7 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
 }
 
 // Q = V Fbar for one 64-row tile and one column plane c (c = M: the z column)
-__global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, TaskMap tm) {
+__global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, double* grad_y, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -253,7 +253,14 @@ __global__ __launch_bounds__(NT) void k_rleaf_q(DevPlan P, TaskMap tm) {
     double* qr = Q + r * T + part * 16;
 #pragma unroll
     for (int j = 0; j < 16; ++j) qr[j] = 0.0;
-    if (part == 0) qr[0] = 0.5 * s - 0.5 * vz[r * T];
+    if (part == 0) {
+      qr[0] = 0.5 * s - 0.5 * vz[r * T];
+      // the data gradient is the z column of Xbar = 2 V Fbar: sum_k V_k wbar^k - v_z
+      if (grad_y) {
+        const int64_t g = P.obs_gidx[p0 + r];
+        if (g >= 0) grad_y[(int64_t)th * P.n + g] = s - vz[r * T];
+      }
+    }
   }
 }
 
@@ -561,14 +568,16 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
 }
 
 // the leaf and prior reverse passes and the final sum (after both of the above)
-hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st) {
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
+                            hipStream_t st) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
-  run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1));
+  run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1),
+            grad_y);
   run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, F.rleaf_sbar, 1, nullptr, k_rleaf_sbar, 0, P.n_sig_tasks,
             theta);
   if (M > 0) {

@@ -187,6 +187,9 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
                                const Side* side = nullptr);
 hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st);
 hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st);
-hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, hipStream_t st);
+// grad_y (may be null): [nth][n] gradient of the log-likelihood with respect
+// to the data, in the caller's order
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
+                            hipStream_t st);
 
 }  // namespace mra

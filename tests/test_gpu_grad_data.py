@@ -1,0 +1,187 @@
+"""GPU parity of the data gradient d loglik / d z = -Sigma^{-1} z, read from
+the z column of the leaves' bordered-step cotangent in the reverse pass,
+against the oracle's kriging-residual form (Prop. 2 at the observed
+locations, a different algorithm).  Bar: 1e-6 relative per entry, plus
+1e-9 of the largest entry for entries near zero.  At full size (n = 2^18)
+the oracle gives 512 sampled entries (tests/golden/, written by
+tests/golden/make_golden.py from the oracle only), and the exact central
+difference of a quadratic form checks every entry at once."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import predict
+from oracle.geometry import Geometry
+from paper_1507_04789_amd import MRAError, MRALogLik, Plan, MRA_GRAPH, MRA_PLAIN, MRA_SYNC
+from paper_1507_04789_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "clustered_n262144_grad_data.json")
+
+
+def _th(s2, k, t2):
+    return np.array([math.log(s2), math.log(k), math.log(t2)])
+
+
+def _check(gy, ref):
+    tol = 1e-6 * np.abs(ref) + 1e-9 * np.abs(ref).max()
+    bad = np.abs(gy - ref) > tol
+    assert not bad.any(), (np.flatnonzero(bad)[:8], gy[bad][:8], ref[bad][:8])
+
+
+def _case(locs, z, kind, th, M, J, r, d=2, flags=MRA_SYNC, knots=None):
+    print("data-gradient case n=%d M=%d J=%d r=%d d=%d %s flags=%d" % (len(z), M, J, r, d, kind, flags), flush=True)
+    p = Plan(locs, M=M, J=J, r=r, cov=kind, d=d, flags=flags, knots=knots)
+    ll, g, gy = p.loglik_grad_data(z, th)
+    ll2, g2 = p.loglik_grad(z, th)
+    # the same kernels: identical log-likelihood and parameter gradient
+    assert torch.equal(ll, ll2) and torch.equal(g, g2)
+    ref = predict.data_gradient(Geometry(locs, d, M, J, r, knots=knots), z, kind, th)
+    _check(gy.cpu().numpy()[0], ref)
+    return p, gy
+
+
+def test_data_grad_m0():
+    g = np.random.default_rng(20)
+    locs = g.random((300, 2))
+    _case(locs, g.standard_normal(300), "matern32", _th(1.2, 0.2, 0.05), 0, 4, 16)
+
+
+@pytest.mark.parametrize("kind", ["matern32", "exponential"])
+@pytest.mark.parametrize("M,r,n", [(1, 16, 1000), (2, 9, 1500), (3, 25, 2500)])
+def test_data_grad_small(kind, M, r, n):
+    g = np.random.default_rng(30 + M)
+    locs = g.random((n, 2))
+    _case(locs, g.standard_normal(n), kind, _th(0.9, 0.15, 0.03), M, 4, r)
+
+
+def test_data_grad_uniform_exponential_m3_r16():
+    w = wl.small_uniform()
+    _case(w.locs, w.z, w.cov, w.theta, w.M, w.J, w.r)
+
+
+def test_data_grad_empty_single_and_large_leaves_plain():
+    g = np.random.default_rng(21)
+    locs = np.concatenate([g.random((700, 2)) * 0.25, g.random((40, 2)) * 0.5 + 0.5, [[0.99, 0.01]]])
+    z = g.standard_normal(locs.shape[0])
+    _case(locs, z, "matern32", _th(1.0, 0.1, 0.01), 3, 4, 16, flags=MRA_SYNC | MRA_PLAIN)
+
+
+def test_data_grad_one_dimensional():
+    """J = 3, r = 2 in 1-D with knots on the boundaries of the next level's
+    cells (the default cell-centred grid would repeat ancestor knots)."""
+    g = np.random.default_rng(22)
+    locs = g.random((400, 1))
+    J, M = 3, 4
+    knots = [np.array([[[i / J ** m + k / J ** (m + 1)] for k in range(1, J)] for i in range(J ** m)])
+             for m in range(M)]
+    _case(locs, g.standard_normal(400), "exponential", _th(1.0, 0.3, 0.05), M, J, 2, d=1, knots=knots)
+
+
+def test_data_grad_batch_graph_and_autograd():
+    """Three parameter vectors in one captured-graph call (replayed with new
+    values in place), and the autograd route: y.grad = sum_t gout_t grad_y_t."""
+    w = wl.clustered(n=16384, M=4)
+    ths = np.stack([w.theta, _th(0.7, 0.05, 0.02), _th(1.5, 0.2, 0.1)])
+    print("data-gradient batch n=%d M=%d, 3 thetas, graph" % (len(w.z), w.M), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=3, flags=MRA_SYNC | MRA_GRAPH)
+    p.bind("cuda:0")
+    geo = Geometry(w.locs, 2, w.M, w.J, w.r)
+    z = torch.tensor(w.z, device="cuda:0")
+    th = torch.tensor(ths, device="cuda:0")
+    out = (torch.empty(3, dtype=torch.float64, device="cuda:0"), torch.empty(3, 3, dtype=torch.float64, device="cuda:0"),
+           torch.empty(3, len(w.z), dtype=torch.float64, device="cuda:0"))
+    p.loglik_grad_data(z, th, out=out)
+    torch.cuda.synchronize()
+    first = out[2].clone()
+    for rep in range(2):   # graph replays
+        out[2].zero_()
+        p.loglik_grad_data(z, th, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out[2], first)
+    gy = out[2].cpu().numpy()
+    for i in range(3):
+        _check(gy[i], predict.data_gradient(geo, w.z, w.cov, ths[i]))
+    # autograd through MRALogLik, with weights on the three log-likelihoods
+    yv = z.clone().requires_grad_(True)
+    tv = th.clone().requires_grad_(True)
+    ll = MRALogLik.apply(tv, p, yv)
+    wts = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda:0")
+    (ll * wts).sum().backward()
+    ref = wts.cpu().numpy() @ gy
+    np.testing.assert_allclose(yv.grad.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_data_grad_rejects_null_and_no_grad_plan():
+    from paper_1507_04789_amd import MRA_NO_GRAD, _lib
+    g = np.random.default_rng(23)
+    locs = g.random((500, 2))
+    z = torch.tensor(g.standard_normal(500), device="cuda:0")
+    p = Plan(locs, M=2, J=4, r=9, cov="matern32")
+    p.bind("cuda:0")
+    th = torch.tensor(_th(1.0, 0.1, 0.05)[None], device="cuda:0")
+    ll = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    gr = torch.empty(1, 3, dtype=torch.float64, device="cuda:0")
+    s = _lib.lib().mra_loglik_grad_data(p._h, z.data_ptr(), th.data_ptr(), 1, ll.data_ptr(), gr.data_ptr(), None,
+                                        p._stream())
+    assert s == -1   # MRA_EINVAL
+    q = Plan(locs, M=2, J=4, r=9, cov="matern32", flags=MRA_SYNC | MRA_NO_GRAD)
+    with pytest.raises(MRAError):
+        q.loglik_grad_data(z, th)
+
+
+def test_data_grad_full_size():
+    """n = 2^18 clustered workload, asynchronous plan as the benchmark runs
+    it: 512 oracle entries, and for every entry at once the exact identity
+    loglik(z + v) - loglik(z - v) = 2 v' grad_y (the log-likelihood is
+    quadratic in z)."""
+    with open(GOLD) as f:
+        gold = json.load(f)
+    w = wl.clustered()
+    assert np.allclose(w.theta, gold["theta"], rtol=0, atol=0)
+    print("data-gradient full size n=%d M=%d" % (len(w.z), w.M), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=0)
+    p.bind("cuda:0")
+    z = torch.tensor(w.z, device="cuda:0")
+    th = torch.tensor(np.asarray(w.theta)[None], device="cuda:0")
+    ll, g, gy = p.loglik_grad_data(z, th)
+    torch.cuda.synchronize()
+    gy = gy.cpu().numpy()[0]
+    idx = np.asarray(gold["index"])
+    _check(gy[idx], np.asarray(gold["grad_y"]))
+    v = torch.tensor(np.random.default_rng(78).standard_normal(len(w.z)), device="cuda:0")
+    lp = float(p.loglik(z + v, th)[0])
+    lm = float(p.loglik(z - v, th)[0])
+    lhs, rhs = lp - lm, 2.0 * float(v.cpu().numpy() @ gy)
+    assert abs(lhs - rhs) <= 1e-8 * (abs(lp) + abs(lm)), (lhs, rhs)
+    del p
+    torch.cuda.empty_cache()
+
+
+def test_fit_small_uniform_reaches_oracle_stationary_point():
+    """Maximum-likelihood fit through the library (L-BFGS, four step lengths
+    per batched call) on the 4096-point exponential workload: the estimate
+    is a stationary point of the oracle's log-likelihood too, and no
+    coordinate perturbation of it raises the library's log-likelihood."""
+    from oracle import mra
+    w = wl.small_uniform()
+    print("fit case n=%d M=%d r=%d %s" % (len(w.z), w.M, w.r, w.cov), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=4)
+    th0 = np.asarray(w.theta) + np.array([0.4, -0.3, 0.5])
+    r = p.fit(w.z, th0, batch=4)
+    assert r.converged, r.message
+    assert r.calls < 100
+    geo = Geometry(w.locs, 2, w.M, w.J, w.r)
+    rll, rg, _ = mra.loglik(geo, w.z, w.cov, r.theta, grad=True)
+    assert abs(r.loglik - rll) <= 1e-10 * abs(rll)
+    # |oracle gradient| at the estimate is at the driver's tolerance, far below the start's
+    g0 = mra.loglik(geo, w.z, w.cov, th0, grad=True)[1]
+    assert np.abs(rg).max() <= max(1e-6 * np.abs(g0).max(), 2e-9 * abs(rll)), (rg, g0)
+    pert = r.theta[None, :] + np.concatenate([np.eye(3), -np.eye(3)]) * 1e-3
+    lls = np.concatenate([p.loglik(w.z, pert[:3]).cpu().numpy(), p.loglik(w.z, pert[3:]).cpu().numpy()])
+    assert (lls <= r.loglik).all()
