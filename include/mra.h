@@ -189,9 +189,14 @@ mra_status mra_last_failure(mra_plan_t plan, int32_t* theta_idx, int32_t* level,
  * planes of one leaf, on one XCD and L2) or "chunked" (one contiguous run of
  * the tree-ordered task list per XCD); "default" keeps the built-in choice.
  * big_leaf_tiles is the tile count from which a leaf is factored on the
- * second stream (0: none); side_solves (0 or 1) puts the reverse pass's leaf
- * solves on the second stream.  Shapes only permute work: results are the same
- * bit for bit under every table.
+ * second stream (0: none).  side_solves places the reverse pass's leaf
+ * solves: 0 on the main stream; s >= 1 on the second stream, forked once the
+ * recursion has reached stage s - 1 (0: before the leaf reduction, 1: after
+ * it, 1 + j: after posterior level M - j, M + 2 + m: after the reverse
+ * posterior step of level m; larger values fork after the last of those), so
+ * that they fill the GPU while the coarse levels' latency-bound steps run.
+ * Shapes only permute work: results are the same bit for bit under every
+ * table.
  *
  * mra_autotune times mra_loglik_grad (mra_loglik for MRA_NO_GRAD plans) on
  * the given device data, `reps` calls per candidate after one warm-up call,

@@ -48,15 +48,16 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
 hipError_t ensure_side(mra_plan_s* H) {
   if (H->side_stream) return hipSuccess;
   hipStream_t s2;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  constexpr int NEV = 5;
+  hipEvent_t ev[NEV] = {};
   hipError_t e;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NEV; ++i)
     if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
       return e;
     }
   if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess) {
-    for (int j = 0; j < 4; ++j) (void)hipEventDestroy(ev[j]);
+    for (int j = 0; j < NEV; ++j) (void)hipEventDestroy(ev[j]);
     return e;
   }
   H->side_stream = s2;
@@ -64,12 +65,13 @@ hipError_t ensure_side(mra_plan_s* H) {
   H->ev_big = ev[1];
   H->ev_fork2 = ev[2];
   H->ev_join = ev[3];
+  H->ev_join2 = ev[4];
   return hipSuccess;
 }
 
 Side side_of(const mra_plan_s* H) {
   return Side{(hipStream_t)H->side_stream, (hipEvent_t)H->ev_fork, (hipEvent_t)H->ev_big, (hipEvent_t)H->ev_fork2,
-              (hipEvent_t)H->ev_join};
+              (hipEvent_t)H->ev_join, (hipEvent_t)H->ev_join2};
 }
 
 }  // namespace
@@ -144,21 +146,36 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   const Side sd = side_of(H);
   const Side* side = overlap ? &sd : nullptr;
   if ((e = launch_forward_front(*H, y, theta, nth, st, side)) != hipSuccess) return e;
-  const bool on_side = side && H->side_solves;
-  if (on_side) {
-    // leaf solves on the side stream, after the small leaves (fork2) and,
-    // in stream order, after the large ones
-    if ((e = hipEventRecord(sd.fork2, st)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(sd.s, sd.fork2, 0)) != hipSuccess) return e;
-  } else if (side && H->nbig() > 0) {
-    if ((e = hipStreamWaitEvent(st, sd.big, 0)) != hipSuccess) return e;   // they need every leaf
+  const bool on_side = side && H->side_solves > 0;
+  if (!on_side) {
+    if (side && H->nbig() > 0 && (e = hipStreamWaitEvent(st, sd.big, 0)) != hipSuccess) return e;   // every leaf
+    if ((e = launch_grad_leafsolve(*H, nth, st)) != hipSuccess) return e;
   }
-  if ((e = launch_grad_leafsolve(*H, nth, on_side ? sd.s : st)) != hipSuccess) return e;
-  if (on_side && (e = hipEventRecord(sd.join, sd.s)) != hipSuccess) return e;
-  if ((e = launch_forward_back(*H, nth, ll, st, side)) != hipSuccess) return e;
-  if ((e = launch_grad_post(*H, nth, st)) != hipSuccess) return e;
+  // otherwise the leaf solves go on the side stream at stage side_solves - 1
+  // of the recursion (ForkHook; event fork2): after the small leaves on the
+  // main stream and, in stream order, after the large ones on the side
+  // stream.  They only read the leaf factors and Y and write V and L^{-1},
+  // which nothing on the main stream touches before the joins (join before
+  // the first use of V, join2 before that of L^{-1}).
+  struct Ctx {
+    mra_plan_s* H;
+    const Side* sd;
+    hipStream_t st;
+    int nth;
+  } ctx{H, &sd, st, nth};
+  ForkHook hook{H->side_solves - 1, [](void* p) -> hipError_t {
+    const Ctx& c = *static_cast<const Ctx*>(p);
+    hipError_t r;
+    if ((r = hipEventRecord(c.sd->fork2, c.st)) != hipSuccess) return r;
+    if ((r = hipStreamWaitEvent(c.sd->s, c.sd->fork2, 0)) != hipSuccess) return r;
+    if ((r = launch_grad_leafsolve(*c.H, c.nth, c.sd->s, c.sd->join)) != hipSuccess) return r;
+    return hipEventRecord(c.sd->join2, c.sd->s);
+  }, &ctx, false};
+  ForkHook* hk = on_side ? &hook : nullptr;
+  if ((e = launch_forward_back(*H, nth, ll, st, side, hk)) != hipSuccess) return e;
+  if ((e = launch_grad_post(*H, nth, st, hk)) != hipSuccess) return e;
   if (on_side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
-  return launch_grad_rest(*H, theta, nth, g, gy, st);
+  return launch_grad_rest(*H, theta, nth, g, gy, st, on_side ? sd.join2 : nullptr);
 }
 
 // ---- tuning table (JSON) ----
@@ -445,7 +462,7 @@ mra_status mra_set_tuning(mra_plan_t P, const char* json) {
   int32_t sides = P->side_solves;
   if (json_value(json, "side_solves", v)) {
     sides = std::atoi(v.c_str());
-    if (sides != 0 && sides != 1) return MRA_EINVAL;
+    if (sides < 0 || sides > 64) return MRA_EINVAL;
   }
   std::memcpy(P->tune, t, sizeof t);
   P->big_tiles = big;
@@ -526,12 +543,17 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
     P->big_tiles = pick;
     if (grad) {
       const int32_t keep_s = P->side_solves;
-      P->side_solves = 1 - keep_s;
-      const double t = measure();
-      if (t < best * 0.995)
-        best = t;
-      else
-        P->side_solves = keep_s;
+      int32_t pick_s = keep_s;
+      for (int32_t v = 0; v <= 2 * P->M + 2 && ok; ++v) {
+        if (v == keep_s) continue;
+        P->side_solves = v;
+        const double t = measure();
+        if (t < best * 0.995) {
+          best = t;
+          pick_s = v;
+        }
+      }
+      P->side_solves = pick_s;
     }
   }
   (void)hipEventDestroy(e0);
@@ -612,7 +634,7 @@ void mra_destroy(mra_plan_t P) {
     (void)hipStreamSynchronize((hipStream_t)P->side_stream);
     (void)hipStreamDestroy((hipStream_t)P->side_stream);
   }
-  for (void* ev : {P->ev_fork, P->ev_big, P->ev_fork2, P->ev_join})
+  for (void* ev : {P->ev_fork, P->ev_big, P->ev_fork2, P->ev_join, P->ev_join2})
     if (ev) (void)hipEventDestroy((hipEvent_t)ev);
   if (P->graphs) {
     P->graphs->clear();

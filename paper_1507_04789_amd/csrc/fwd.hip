@@ -434,17 +434,18 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
 // leaf products, posterior recursion and the log-likelihood.  With large
 // leaves on the side stream, the parents whose children are all small go
 // first; the main stream then waits for the large leaves.
-hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st, const Side* side) {
+hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st, const Side* side,
+                               ForkHook* hook) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const bool split = side && H.nbig() > 0;
+  auto at = [&](int stage) -> hipError_t { return hook ? hook->at(stage) : hipSuccess; };
+  hipError_t e = at(0);
+  if (e != hipSuccess) return e;
   if (M == 0) {
-    if (split) {
-      hipError_t e = hipStreamWaitEvent(st, side->big, 0);
-      if (e != hipSuccess) return e;
-    }
+    if (split && (e = hipStreamWaitEvent(st, side->big, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {
     const int nkl = M * (M + 1) / 2;
@@ -453,19 +454,21 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
     const double f0 = ntask ? F.leaf_reduce * (double)cut / (double)ntask : 0.0;
     run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, f0, nkl, nullptr, k_leaf_reduce, 0, cut);
     if (split) {
-      hipError_t e = hipStreamWaitEvent(st, side->big, 0);
-      if (e != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, side->big, 0)) != hipSuccess) return e;
       run.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce_big", -1, F.leaf_reduce - f0, nkl, nullptr, k_leaf_reduce,
                 cut, ntask);
     }
+    if ((e = at(1)) != hipSuccess) return e;
     for (int m = M - 1; m >= 0; --m) {
       run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, H.nact_post(m), m, out_loglik);
       if (m > 0)
         run.tuned(F_POST_REDUCE, MAP_GROUPED, "post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, nullptr,
                   k_post_reduce, 0, H.nact_post(m - 1) * (int64_t)(m * (m + 1) / 2), m);
+      if ((e = at(1 + M - m)) != hipSuccess) return e;
     }
   }
   if (out_loglik) hipLaunchKernelGGL(k_mark_failed, dim3(nth), dim3(64), 0, st, P, out_loglik, 1);
+  if (M == 0 && (e = at(M + 1)) != hipSuccess) return e;
   return hipGetLastError();
 }
 

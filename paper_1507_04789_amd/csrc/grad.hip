@@ -541,20 +541,24 @@ __global__ void k_zero_gpart(DevPlan P, int64_t nslot) {
 // leaf solves of the reverse pass that only need the forward leaf factors:
 // V = L_Sigma^{-T} Y and L_Sigma^{-1}; may run on a second stream while the
 // posterior recursion proceeds
-hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st) {
+hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st, hipEvent_t after_v) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   run.tuned(F_RLEAF_V, MAP_GROUPED, "rleaf_v", -1, F.rleaf_v, M + 1, nullptr, k_rleaf_v, 0,
             (int64_t)H.trsm_tasks.size() / 2);
+  if (after_v) {
+    const hipError_t e = hipEventRecord(after_v, st);
+    if (e != hipSuccess) return e;
+  }
   run.tuned(F_RLEAF_LINV, MAP_IDENTITY, "rleaf_linv", -1, F.rleaf_linv, 1, nullptr, k_rleaf_linv, 0,
             (int64_t)H.linv_tasks.size() / 2);
   return hipGetLastError();
 }
 
 // the posterior reverse pass (after the forward log-likelihood)
-hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -562,14 +566,18 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st) {
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
-  for (int m = 0; m < M; ++m)
+  hipError_t e;
+  for (int m = 0; m < M; ++m) {
     run.tuned(F_RPOST, MAP_IDENTITY, "rpost", m, F.rpost[m], 1, nullptr, k_rpost, 0, H.nact_post(m), m);
+    if (hook && (e = hook->at(M + 2 + m)) != hipSuccess) return e;
+  }
+  if (hook && (e = hook->at(0, true)) != hipSuccess) return e;
   return hipGetLastError();
 }
 
 // the leaf and prior reverse passes and the final sum (after both of the above)
 hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t wait_linv) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -578,6 +586,10 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, d
   const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1),
             grad_y);
+  if (wait_linv) {
+    const hipError_t e = hipStreamWaitEvent(st, wait_linv, 0);
+    if (e != hipSuccess) return e;
+  }
   run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, F.rleaf_sbar, 1, nullptr, k_rleaf_sbar, 0, P.n_sig_tasks,
             theta);
   if (M > 0) {

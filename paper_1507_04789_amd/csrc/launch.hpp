@@ -179,17 +179,36 @@ hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* th
 // join).  A null Side runs everything on the main stream.
 struct Side {
   hipStream_t s;
-  hipEvent_t fork, big, fork2, join;
+  hipEvent_t fork, big, fork2, join, join2;   // join: V done; join2: L^{-1} done
 };
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
                                 const Side* side = nullptr);
+// A callback run once, when the launches of its stage have been enqueued on
+// the main stream: 0 before the leaf reduction, 1 after it, 1 + j after
+// posterior level M - j (and its child sums), j = 1..M, then M + 2 + m after
+// the reverse posterior step of level m, m = 0..M-1; a later stage runs at
+// the end of the reverse posterior.  Used to fork independent work onto the
+// side stream at a chosen point of the recursion.
+struct ForkHook {
+  int stage;
+  hipError_t (*fn)(void* ctx);
+  void* ctx;
+  bool fired;
+  hipError_t at(int s, bool last = false) {
+    if (fired || (!last && s < stage)) return hipSuccess;
+    fired = true;
+    return fn(ctx);
+  }
+};
 hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik, hipStream_t st,
-                               const Side* side = nullptr);
-hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st);
-hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st);
+                               const Side* side = nullptr, ForkHook* hook = nullptr);
+// after_v (may be null) is recorded on st once V is written, before L^{-1}
+hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st, hipEvent_t after_v = nullptr);
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook = nullptr);
 // grad_y (may be null): [nth][n] gradient of the log-likelihood with respect
 // to the data, in the caller's order
+// wait_linv (may be null): event to wait for before the first use of L^{-1}
 hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
-                            hipStream_t st);
+                            hipStream_t st, hipEvent_t wait_linv = nullptr);
 
 }  // namespace mra

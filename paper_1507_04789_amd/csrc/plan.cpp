@@ -99,6 +99,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   }
   P->cfg = *cfg;
   P->d = d; P->M = M; P->J = J; P->r = r; P->n = n; P->n_pred = n_pred;
+  P->side_solves = M + 2;   // leaf solves forked once the forward recursion is enqueued
   // levels
   P->nreg.assign(M + 1, 1);
   for (int m = 1; m <= M; ++m) P->nreg[m] = P->nreg[m - 1] * J;

@@ -67,7 +67,9 @@ struct mra_plan_s {
   // the tile count from which a leaf is factored on the side stream (0: none)
   uint8_t tune[32] = {};
   int32_t big_tiles = 3;
-  int32_t side_solves = 1;   // reverse-pass leaf solves on the side stream (1) or the main stream (0)
+  // reverse-pass leaf solves: on the main stream (0), or on the side stream
+  // forked at stage side_solves - 1 of the posterior recursion (ForkHook)
+  int32_t side_solves = 2;   // set to M + 2 by build_plan
   // pruning: a region of level m < M is active for the posterior and the
   // reverse pass when observations lie below it, and for the prior when
   // observations or prediction points do; the others get no storage and no
@@ -105,7 +107,8 @@ struct mra_plan_s {
   void* ev_fork = nullptr;       // hipEvent_t: main -> side, large leaves' factorisation
   void* ev_big = nullptr;        //   side -> main, large leaves done
   void* ev_fork2 = nullptr;      //   main -> side, reverse-pass leaf solves
-  void* ev_join = nullptr;       //   side -> main, leaf solves done
+  void* ev_join = nullptr;       //   side -> main, V = L^{-T} Y done
+  void* ev_join2 = nullptr;      //   side -> main, L^{-1} done
   int32_t last_nth = 1;
 };
 

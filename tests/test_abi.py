@@ -111,14 +111,17 @@ def test_tuning_table_roundtrip():
     g = np.random.default_rng(5)
     p = Plan(g.random((500, 2)), M=2, J=4, r=9, cov="exponential")
     t = p.tuning()
-    assert t["big_leaf_tiles"] == 3 and t["side_solves"] == 1 and set(t["families"].values()) == {"default"}
+    assert t["big_leaf_tiles"] == 3 and t["side_solves"] == 2 + 2 and set(t["families"].values()) == {"default"}
     t["families"]["leaf_rows"] = "identity"
     t["families"]["rT_leaf"] = "chunked"
     t["big_leaf_tiles"] = 0
+    t["side_solves"] = 1
     p.set_tuning(t)
     u = p.tuning()
     assert u["families"]["leaf_rows"] == "identity" and u["families"]["rT_leaf"] == "chunked"
-    assert u["big_leaf_tiles"] == 0
+    assert u["big_leaf_tiles"] == 0 and u["side_solves"] == 1
+    with pytest.raises(MRAError):
+        p.set_tuning({"side_solves": -1})
     with pytest.raises(MRAError):
         p.set_tuning({"families": {"post": "sideways"}})
     with pytest.raises(MRAError):

@@ -30,7 +30,7 @@ def test_autotune_keeps_results_bitwise():
         for f in t["families"]:
             t["families"][f] = shape
         t["big_leaf_tiles"] = [0, 2, 4][k]
-        t["side_solves"] = k % 2
+        t["side_solves"] = [0, 3, w.M + 2][k]   # main stream; forked after the top level; at the end
         p.set_tuning(t)
         ll2, g2 = p.loglik_grad(z, th)
         assert torch.equal(ll0, ll2) and torch.equal(g0, g2), shape
