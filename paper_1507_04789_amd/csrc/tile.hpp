@@ -498,53 +498,51 @@ __device__ __forceinline__ double rsqrt_d(double p) {
   return y;
 }
 
-// Lower Cholesky of the 16x16 block D (pitch PLD) in place, left-looking, by
-// lanes 0..15 of one wave: lane i keeps row i in registers; row j of the
-// factor is read back from LDS as a broadcast (a wave's LDS accesses complete
-// in order, so column j is visible to every lane in the next step).  rdiag[j]
-// receives 1/L_jj.  Upper part zeroed.  Returns 1 if every pivot was positive
-// (uniform over the wave).
-__device__ __forceinline__ int potrf16(double* D, double* rdiag) {
+// Lower Cholesky of the 16x16 block D (pitch PLD) and the inverse of the
+// factor in one right-looking sweep, by lanes 0..15 of one wave: lane i keeps
+// row i of the working block (a) and of the inverse (x) in registers.  Step j
+// takes the pivot from lane j, forms column j of the factor, then updates the
+// trailing columns with column j (a_ik -= L_ij L_kj, k > j) and the inverse
+// rows below j with row j of the inverse (x_i -= L_ij x_j, the forward
+// substitution of L X = I); both operands are broadcast by readlane, so the
+// loop touches no LDS.  On return D holds L (zero above the diagonal) and X
+// (pitch ldx) holds L^{-1}.  Returns 0 if a pivot was not positive (the
+// outputs then carry NaN).
+__device__ __forceinline__ int potrf_trtri16(double* D, double* X, int ldx) {
   const int i = lane_id();
   const bool own = i < 16;
-  double row[16];
+  double a[16], x[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) row[k] = own ? D[i * PLD + k] : 0.0;
+  for (int k = 0; k < 16; ++k) {
+    a[k] = own ? D[i * PLD + k] : 0.0;
+    x[k] = (i == k) ? 1.0 : 0.0;
+  }
   int ok = 1;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    double a = row[j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) a = fma(-row[k], D[j * PLD + k], a);
-    const double p = readlane_d(a, j);
+    const double p = readlane_d(a[j], j);
     ok &= (p > 0.0) ? 1 : 0;
     const double y = (p > 0.0) ? rsqrt_d(p) : __builtin_nan("");
-    row[j] = (i > j) ? a * y : (i == j ? p * y : 0.0);
-    if (own) D[i * PLD + j] = row[j];
-    if (i == j) rdiag[j] = y;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_sched_barrier(0);
+    const double l = (i > j) ? a[j] * y : (i == j ? p * y : 0.0);   // L_ij
+    a[j] = l;
+    // row j of the inverse is final once scaled by 1 / L_jj
+    const double sj = (i == j) ? y : 1.0;
+#pragma unroll
+    for (int c = 0; c <= j; ++c) x[c] *= sj;
+    const double lb = (i > j) ? l : 0.0;
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) a[k] = fma(-lb, readlane_d(l, k), a[k]);
+#pragma unroll
+    for (int c = 0; c <= j; ++c) x[c] = fma(-lb, readlane_d(x[c], j), x[c]);
+  }
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      D[i * PLD + k] = (k <= i) ? a[k] : 0.0;
+      X[i * ldx + k] = x[k];
+    }
   }
   return ok;
-}
-
-// X (pitch ldx) = inverse of the lower-triangular 16x16 block D (pitch PLD),
-// by lanes 0..15 of one wave (lane j computes column j); rdiag = 1/diag(D)
-__device__ __forceinline__ void trtri16(const double* D, const double* rdiag, double* X, int ldx) {
-  const int j = lane_id();
-  if (j < 16) {
-    double x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double acc = (r == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < r; ++k) acc = fma(-D[r * PLD + k], x[k], acc);
-      x[r] = acc * rdiag[r];
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) X[r * ldx + j] = x[r];
-  }
 }
 
 // Blocked lower Cholesky of the symmetric 64x64 tile in s (lower triangle
@@ -558,7 +556,6 @@ __device__ __forceinline__ void trtri16(const double* D, const double* rdiag, do
 // inverse then carry NaN.
 __device__ inline bool potrf_trtri(double* s, double* sx, double* Linv) {
   __shared__ int ok_all;
-  __shared__ double rdiag[T];
   const int w = wave_id();
   if (threadIdx.x == 0) ok_all = 1;
   for (int e = threadIdx.x; e < TT; e += NT) sx[(e >> 6) * PLD + (e & 63)] = 0.0;
@@ -567,9 +564,8 @@ __device__ inline bool potrf_trtri(double* s, double* sx, double* Linv) {
     double* Dk = s + 16 * kb * PLD + 16 * kb;
     double* Xk = sx + 16 * kb * PLD + 16 * kb;
     if (w == 0) {
-      const int ok = potrf16(Dk, rdiag + 16 * kb);
+      const int ok = potrf_trtri16(Dk, Xk, PLD);
       if (lane_id() == 0 && !ok) ok_all = 0;
-      trtri16(Dk, rdiag + 16 * kb, Xk, PLD);
     }
     __syncthreads();
     const int ib = kb + 1 + w;                 // panel: L_ik = A_ik X_kk^T
