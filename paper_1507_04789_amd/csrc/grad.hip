@@ -173,7 +173,9 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   }
 }
 
-// tile column j of L_Sigma^{-1} (forward substitution of the identity)
+// tile column j < nb - 1 of L_Sigma^{-1} below the diagonal (forward
+// substitution of the identity); the diagonal tiles are the inverses the
+// factorisation keeps, read in place
 __global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
@@ -188,14 +190,12 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
   const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
   double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
   Acc acc;
-  acc_load(acc, dinv + (int64_t)j * TT, T);
-  acc_store(acc, Li + ((int64_t)j * nb + j) * TT, T);
-  __syncthreads();
   for (int ib = j + 1; ib < nb; ++ib) {
     acc_zero(acc);
     gemm_segs(acc, ib - j, [&](int q) {
       const int kb = j + q;
-      return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + kb) * TT, T, Li + ((int64_t)kb * nb + j) * TT, T, -1.0);
+      const double* Xkj = kb == j ? dinv + (int64_t)j * TT : Li + ((int64_t)kb * nb + j) * TT;
+      return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + kb) * TT, T, Xkj, T, -1.0);
     }, lds);
     double* out = Li + ((int64_t)ib * nb + j) * TT;
     acc_store(acc, out, T);
@@ -282,6 +282,9 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   const int nR = P.leaf_n[leaf];
   const int64_t pi = poff + (int64_t)T * bi, pj = poff + (int64_t)T * bj;
   const double* Li = S + P.off_linv + P.leaf_soff[leaf] * TT;
+  const double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
+  // tile (r, c) of L^{-1}: the diagonal ones are the factorisation's inverses
+  auto li = [&](int r, int c) { return r == c ? dinv + (int64_t)r * TT : Li + ((int64_t)r * nb + c) * TT; };
   const int nvi = min(T, nR - T * bi), nvj = min(T, nR - T * bj);
   Acc acc;
   acc_zero(acc);
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
     if (q <= P.M)
       return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0);
     const int kb = bi + q - (P.M + 1);
-    return seg<Op::T, Op::N>(Li + ((int64_t)kb * nb + bi) * TT, T, Li + ((int64_t)kb * nb + bj) * TT, T, -0.5);
+    return seg<Op::T, Op::N>(li(kb, bi), T, li(kb, bj), T, -0.5);
   }, lds, round16(nvi), round16(nvj));
   double* out = S + P.off_sbar + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT;
   acc_store(acc, out, T);

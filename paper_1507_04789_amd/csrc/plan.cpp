@@ -214,7 +214,8 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
         P->sig_tasks.push_back(i); P->sig_tasks.push_back((int32_t)bi); P->sig_tasks.push_back((int32_t)bj);
       }
     for (int c = 0; c <= M; ++c) { P->trsm_tasks.push_back(i); P->trsm_tasks.push_back(c); }
-    for (int64_t j = 0; j < nb; ++j) { P->linv_tasks.push_back(i); P->linv_tasks.push_back((int32_t)j); }
+    // tile columns of L^{-1} with tiles below the diagonal
+    for (int64_t j = 0; j + 1 < nb; ++j) { P->linv_tasks.push_back(i); P->linv_tasks.push_back((int32_t)j); }
   }
   // row tiles in tree order (leaf index order is depth-first), so that
   // consecutive tasks share ancestors
