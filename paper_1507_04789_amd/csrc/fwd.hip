@@ -174,15 +174,18 @@ __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
   Acc acc;
   for (int ib = 0; ib < nb; ++ib) {
     const int mr = round16(min(T, nR - T * ib));
-    acc_load(acc, X + (int64_t)ib * TT, T);
-    gemm_segs2(acc, ib,
-              [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
-              lds, mr);
-    acc_store(acc, Y + (int64_t)ib * TT, T);
-    __syncthreads();
+    const double* R = X + (int64_t)ib * TT;   // right-hand side after the updates
+    if (ib > 0) {
+      acc_load(acc, R, T);
+      gemm_segs2(acc, ib,
+                [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
+                lds, mr);
+      acc_store(acc, Y + (int64_t)ib * TT, T);
+      __syncthreads();
+      R = Y + (int64_t)ib * TT;
+    }
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, Y + (int64_t)ib * TT, T, 1.0); },
-              lds, mr);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr);
     acc_store(acc, Y + (int64_t)ib * TT, T);
     __syncthreads();
   }

@@ -158,16 +158,19 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   Acc acc;
   for (int ib = nb - 1; ib >= 0; --ib) {
     const int mr = round16(min(T, nR - T * ib));
-    acc_load(acc, Y + (int64_t)ib * TT, T);
-    gemm_segs2(acc, nb - 1 - ib, [&](int q) {
-      const int jb = ib + 1 + q;
-      return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
-    }, lds, mr);
-    acc_store(acc, V + (int64_t)ib * TT, T);
-    __syncthreads();
+    const double* R = Y + (int64_t)ib * TT;   // right-hand side after the updates
+    if (ib < nb - 1) {
+      acc_load(acc, R, T);
+      gemm_segs2(acc, nb - 1 - ib, [&](int q) {
+        const int jb = ib + 1 + q;
+        return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
+      }, lds, mr);
+      acc_store(acc, V + (int64_t)ib * TT, T);
+      __syncthreads();
+      R = V + (int64_t)ib * TT;
+    }
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, V + (int64_t)ib * TT, T, 1.0); },
-              lds, mr);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr);
     acc_store(acc, V + (int64_t)ib * TT, T);
     __syncthreads();
   }
