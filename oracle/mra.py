@@ -177,13 +177,20 @@ def _zero_like_blocks(M, r, grad):
     return At, om, z(()), z(())
 
 
-def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bool = False):
+def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bool = False,
+           child_order: str = "forward"):
     """M-RA log-likelihood (and its gradient in log-parameters).
 
     Returns (loglik, grad or None, state).  z is in the original order of
     the locations given to geom.  state holds the recursion's quantities when
-    keep is True (prediction needs them).
+    keep is True (prediction needs them).  child_order = "reversed" visits
+    the regions of each level, and so sums every parent's children, in the
+    opposite order: an equally valid operation order, used to measure the
+    rounding spread of the result.
     """
+    if child_order not in ("forward", "reversed"):
+        raise ValueError("child_order must be 'forward' or 'reversed'")
+    order = (lambda n: range(n)) if child_order == "forward" else (lambda n: range(n - 1, -1, -1))
     cov = Covariance(cov_kind, theta)
     M, J, r = geom.M, geom.J, geom.r
     z = np.asarray(z, dtype=np.float64)
@@ -197,7 +204,7 @@ def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bo
     # leaves and the first posterior level: each level-(M-1) region sums its
     # children's leaf quantities (eq. mainquantities)
     child_sum = {}
-    for i in range(J ** M):
+    for i in order(J ** M):
         Ws = prior_region(geom, cov, st, M, i, grad)
         zR = z[geom.leaf_obs(i)]
         if zR.shape[0] == 0:
@@ -216,7 +223,7 @@ def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bo
         return ll, g, st
     # posterior recursion, bottom-up (eq. posterior, helpquantities, Sec. 3.3)
     for m in range(M - 1, -1, -1):
-        for i in range(J ** m):
+        for i in order(J ** m):
             A, om, dsum, usum = child_sum.pop((m, i))
             Kinv = st.Kinv[(m, i)]
             Kt = SPD(Kinv.A + A[(m, m)])

@@ -339,3 +339,21 @@ def test_data_gradient_m0_textbook():
     ref = -np.linalg.solve(cov(locs, locs) + cov.tau2 * np.eye(120), z)
     np.testing.assert_allclose(predict.data_gradient(g, z, "matern32", th), ref, rtol=1e-9,
                                atol=1e-10 * np.abs(ref).max())
+
+
+# Noise floor: two valid operation orders of the oracle (children summed
+# forward and reversed at every level) on a clustered r = 64 workload.  The
+# spread of the log-likelihood and of the gradient is the floor that the
+# GPU parity bars (1e-10 and 1e-6 relative) sit far above.
+def test_noise_floor_child_order():
+    from paper_1507_04789_amd import workloads as wl
+    w = wl.clustered(n=4096, M=3)
+    geo = Geometry(w.locs, 2, w.M, w.J, w.r)
+    a, ga, _ = mra.loglik(geo, w.z, w.cov, w.theta, grad=True)
+    b, gb, _ = mra.loglik(geo, w.z, w.cov, w.theta, grad=True, child_order="reversed")
+    spread = abs(a - b) / abs(a)
+    gspread = np.max(np.abs(ga - gb) / np.abs(ga))
+    print("noise floor: loglik %.3g, gradient %.3g (relative)" % (spread, gspread))
+    assert spread <= 1e-12 and gspread <= 1e-9
+    with pytest.raises(ValueError):
+        mra.loglik(geo, w.z, w.cov, w.theta, child_order="sideways")
