@@ -16,8 +16,9 @@ datasets" (JASA 2017, arXiv 1507.04789), in the paper's own notation:
                  log-likelihood d/u recursions (Sec. 3.3) and a forward-mode
                  (tangent) gradient of all of it
   predict.py     posterior predictive mean and variance (Sec. 3.4, Prop. 2),
-                 and the data gradient d loglik / d z = -Sigma^{-1} z from
-                 the kriging residual at the observed locations
+                 the data gradient d loglik / d z = -Sigma^{-1} z from
+                 the kriging residual at the observed locations, and the
+                 generalised least-squares trend with its profile likelihood
   dense.py       brute-force n x n M-RA covariance from the closed form of
                  Sec. 2.4 ("Quality of the covariance approximation"), dense
                  likelihood, gradient and kriging; exact Gaussian process

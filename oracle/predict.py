@@ -101,3 +101,26 @@ def data_gradient(geom: Geometry, z, cov_kind, theta, idx=None):
     cov = Covariance(cov_kind, theta)
     mean, _ = predict(geom, z, cov_kind, theta, geom.locs[idx])
     return (mean - z[idx]) / cov.tau2
+
+
+def gls(geom: Geometry, z, X, cov_kind, theta):
+    """Generalised least squares for a mean trend z = X beta + (M-RA field
+    with measurement error): beta = (X' Sigma^{-1} X)^{-1} X' Sigma^{-1} z,
+    the profile log-likelihood loglik(z - X beta; theta) and its gradient in
+    the log-parameters.  The paper removes the mean before the M-RA and
+    states the model for a zero-mean field; a linear trend is the usual
+    estimator of that mean.  By the envelope theorem the profile gradient is
+    the gradient at the fixed residual (beta maximises the likelihood for
+    every theta).  Sigma^{-1} v comes from data_gradient (Prop. 2), the
+    likelihood and its gradient from mra.loglik (Sec. 3.3).
+
+    Returns (beta, loglik, grad, XtSiX).
+    """
+    z = np.asarray(z, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(z.shape[0], -1)
+    SiX = np.stack([-data_gradient(geom, X[:, j], cov_kind, theta) for j in range(X.shape[1])], axis=1)
+    XtSiX = X.T @ SiX
+    XtSiz = SiX.T @ z
+    beta = np.linalg.solve(XtSiX, XtSiz)
+    ll, g, _ = loglik(geom, z - X @ beta, cov_kind, theta, grad=True)
+    return beta, ll, g, XtSiX

@@ -357,3 +357,40 @@ def test_noise_floor_child_order():
     assert spread <= 1e-12 and gspread <= 1e-9
     with pytest.raises(ValueError):
         mra.loglik(geo, w.z, w.cov, w.theta, child_order="sideways")
+
+
+def _trend_data(n, seed):
+    locs, z = _data(n, seed=seed)
+    X = np.stack([np.ones(n), locs[:, 0], locs[:, 1]], axis=1)
+    return locs, z + X @ np.array([0.5, 1.0, -1.0]), X
+
+
+# GLS trend: beta, the profile log-likelihood and its gradient against the
+# dense brute-force Sigma (Sec. 2.4 closed form), independent of the
+# recursions
+@pytest.mark.parametrize("M,r", [(0, 4), (2, 4), (3, 9)])
+def test_gls_matches_dense(M, r):
+    locs, z, X = _trend_data(160, 21)
+    th = _theta(k=0.2, t2=0.05)
+    g = Geometry(locs, 2, M, 4, r)
+    beta, ll, gr, A = predict.gls(g, z, X, "matern32", th)
+    cov = Covariance("matern32", th)
+    V, T = dense.data_covariance(g, cov, grad=True)
+    SiX = np.linalg.solve(V, X)
+    ref_b = np.linalg.solve(X.T @ SiX, SiX.T @ z)
+    np.testing.assert_allclose(beta, ref_b, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(A, X.T @ SiX, rtol=1e-8)
+    rll, rg = dense.gauss_loglik(V, z - X @ ref_b, T)
+    assert abs(ll - rll) <= 1e-9 * abs(rll)
+    np.testing.assert_allclose(gr, rg, rtol=1e-6, atol=1e-8 * np.abs(rg).max())
+
+
+# Envelope theorem: central differences of the profile log-likelihood, with
+# beta re-estimated at every theta, equal the gradient at the fixed residual
+def test_gls_profile_gradient_envelope():
+    locs, z, X = _trend_data(180, 22)
+    th = _theta(k=0.15, t2=0.04)
+    g = Geometry(locs, 2, 2, 4, 9)
+    _, _, gr, _ = predict.gls(g, z, X, "exponential", th)
+    fd = _fd(lambda t: predict.gls(g, z, X, "exponential", t)[1], th, h=1e-5)
+    np.testing.assert_allclose(gr, fd, rtol=1e-5, atol=1e-7 * np.abs(fd).max())
