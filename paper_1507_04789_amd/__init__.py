@@ -183,6 +183,37 @@ class Plan:
         self._fail(s, "mra_loglik_grad_data")
         return out, g, gy
 
+    def gls(self, y, X, theta):
+        """Generalised least-squares mean trend for data y = X beta + (M-RA
+        field with measurement error) at one parameter vector theta (3,):
+        beta = (X' Sigma^{-1} X)^{-1} X' Sigma^{-1} y, the profile
+        log-likelihood loglik(y - X beta; theta) and its gradient.  The
+        gradient at the fixed residual is the profile gradient (beta
+        maximises the likelihood for every theta).
+
+        Sigma^{-1} X comes from the library's data gradient (one
+        mra_loglik_grad_data call per column of X), the profile likelihood
+        from one mra_loglik_grad call at the residual; the p x p normal
+        equations, their right-hand side and the residual are host
+        arithmetic on those results.  Returns a dict with beta (p,),
+        loglik, grad (3,) and XtSiX (p, p)."""
+        torch = _torch()
+
+        def host(a):
+            return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a)
+
+        yh = np.ascontiguousarray(host(y), dtype=np.float64).reshape(-1)
+        Xh = np.ascontiguousarray(host(X), dtype=np.float64).reshape(yh.shape[0], -1)
+        th = np.asarray(host(theta), dtype=np.float64).reshape(1, 3)
+        SiX = np.empty_like(Xh)
+        for j in range(Xh.shape[1]):
+            _, _, gy = self.loglik_grad_data(np.ascontiguousarray(Xh[:, j]), th)
+            SiX[:, j] = -gy[0].cpu().numpy()
+        A = Xh.T @ SiX
+        beta = np.linalg.solve(A, SiX.T @ yh)
+        ll, g = self.loglik_grad(yh - Xh @ beta, th)
+        return {"beta": beta, "loglik": float(ll[0]), "grad": g[0].cpu().numpy(), "XtSiX": A}
+
     def fit(self, y, theta0, *, batch: int | None = None, **kw):
         """Maximum-likelihood estimate of (log sigma^2, log kappa, log tau^2)
         from theta0 by L-BFGS with a batched line search (mle.maximize):

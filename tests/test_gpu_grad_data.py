@@ -185,3 +185,52 @@ def test_fit_small_uniform_reaches_oracle_stationary_point():
     pert = r.theta[None, :] + np.concatenate([np.eye(3), -np.eye(3)]) * 1e-3
     lls = np.concatenate([p.loglik(w.z, pert[:3]).cpu().numpy(), p.loglik(w.z, pert[3:]).cpu().numpy()])
     assert (lls <= r.loglik).all()
+
+
+def _trend(locs):
+    return np.stack([np.ones(len(locs)), locs[:, 0], locs[:, 1]], axis=1)
+
+
+@pytest.mark.parametrize("M,r,n", [(0, 16, 400), (2, 9, 1500), (3, 25, 2500)])
+def test_gls_small_against_oracle(M, r, n):
+    """GLS trend, profile log-likelihood and gradient against the oracle's
+    (Sigma^{-1} X from the kriging residual, likelihood recursion at the
+    residual): beta to 1e-8, loglik to 1e-10, gradient to 1e-6 relative."""
+    g = np.random.default_rng(40 + M)
+    locs = g.random((n, 2))
+    X = _trend(locs)
+    z = g.standard_normal(n) + X @ np.array([0.5, 1.0, -1.0])
+    th = _th(0.9, 0.15, 0.03)
+    print("gls case n=%d M=%d r=%d" % (n, M, r), flush=True)
+    p = Plan(locs, M=M, J=4, r=r, cov="matern32")
+    out = p.gls(z, X, th)
+    rb, rll, rg, rA = predict.gls(Geometry(locs, 2, M, 4, r), z, X, "matern32", th)
+    np.testing.assert_allclose(out["beta"], rb, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(out["XtSiX"], rA, rtol=1e-9)
+    assert abs(out["loglik"] - rll) <= 1e-10 * abs(rll)
+    assert (np.abs(out["grad"] - rg) <= 1e-6 * np.abs(rg) + 1e-9 * np.abs(rg).max()).all(), (out["grad"], rg)
+
+
+def test_gls_full_size_normal_equations():
+    """n = 2^18 clustered workload plus the trend 0.5 + x - y: the residual
+    of the GLS fit satisfies the normal equations X' Sigma^{-1} r = 0 (checked
+    with the data gradient at the residual), and the profile likelihood is
+    at least that of any perturbed beta."""
+    w = wl.clustered()
+    X = _trend(w.locs)
+    z = w.z + X @ np.array([0.5, 1.0, -1.0])
+    print("gls full size n=%d M=%d" % (len(z), w.M), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=0)
+    p.bind("cuda:0")
+    th = np.asarray(w.theta)
+    out = p.gls(z, X, th)
+    r = z - X @ out["beta"]
+    _, _, gy = p.loglik_grad_data(r, th)
+    ne = X.T @ gy[0].cpu().numpy()                    # = -X' Sigma^{-1} r
+    scale = np.abs(X).T @ np.abs(gy[0].cpu().numpy())
+    assert (np.abs(ne) <= 1e-9 * scale).all(), (ne, scale)
+    for d in np.eye(3) * 1e-3:
+        ll = float(p.loglik(z - X @ (out["beta"] + d), th)[0])
+        assert ll <= out["loglik"]
+    del p
+    torch.cuda.empty_cache()
