@@ -6,6 +6,7 @@
  *   - the log-likelihood of data z observed with measurement error
  *     (Sec. 3.3 with the leaf covariance of Sec. 4.2),
  *   - its gradient with respect to theta = (log sigma^2, log kappa, log tau^2),
+ *   - its gradient with respect to the data,
  *   - the posterior predictive mean and variance of the latent process
  *     (Sec. 3.4, Prop. 2),
  * with all floating point in FP64.
@@ -61,7 +62,7 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 #define MRA_PLAIN  2u   /* one kernel launch per region / task (comparison form) */
 #define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
 #define MRA_NO_GRAD 8u  /* mra_loglik and mra_predict only: the work arena leaves out the reverse
-                           pass's buffers, and mra_loglik_grad returns MRA_ESTATE */
+                           pass's buffers, and mra_loglik_grad(_data) return MRA_ESTATE */
 
 /* MRA_GRAPH: the first call with a given (call kind, n_theta, pointer
  * arguments) captures its whole launch sequence, both internal streams
