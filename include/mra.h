@@ -158,13 +158,17 @@ mra_status mra_loglik_grad(mra_plan_t plan, const double* d_y, const double* d_t
  * d_grad_y[n_theta][n] = d loglik / d z = -Sigma(theta)^{-1} z (caller's
  * order; Sigma as for mra_loglik).  It is the z column of the leaves'
  * bordered-step cotangent in the same reverse pass, so it adds no pass of
- * its own.  All outputs are required, in caller-owned device memory that
- * does not overlap d_y.  MRA_EINVAL for a NULL pointer, MRA_ESTATE for a
+ * its own.  Row b of the batch evaluates the data d_y + b * y_stride with
+ * the parameters d_theta[b]: y_stride = 0 gives every row the same data,
+ * y_stride >= n one data vector per row (several data sets, or one data set
+ * with several right-hand sides such as trend columns, in one call).  All
+ * outputs are required, in caller-owned device memory that does not overlap
+ * d_y.  MRA_EINVAL for a NULL pointer or 0 < y_stride < n, MRA_ESTATE for a
  * plan built with MRA_NO_GRAD.
  */
-mra_status mra_loglik_grad_data(mra_plan_t plan, const double* d_y, const double* d_theta,
-                                int32_t n_theta, double* d_loglik, double* d_grad,
-                                double* d_grad_y, void* stream);
+mra_status mra_loglik_grad_data(mra_plan_t plan, const double* d_y, int64_t y_stride,
+                                const double* d_theta, int32_t n_theta, double* d_loglik,
+                                double* d_grad, double* d_grad_y, void* stream);
 
 /*
  * Posterior predictive mean and variance of the latent process y_M at the

@@ -111,7 +111,9 @@ class Plan:
     def _stream(self):
         return _torch().cuda.current_stream(self.device).cuda_stream
 
-    def _prep(self, y, theta):
+    def _prep(self, y, theta, rows=False):
+        """Device tensors for (y, theta).  With rows=True, y may be (k, n):
+        one data vector per parameter row (k = theta rows)."""
         torch = _torch()
         for name, t in (("y", y), ("theta", theta)):
             if isinstance(t, torch.Tensor) and t.dtype != torch.float64:
@@ -124,7 +126,11 @@ class Plan:
         self._ensure(y)
         y = y.to(self.device).contiguous()
         theta = theta.to(self.device).reshape(-1, 3).contiguous()
-        if y.numel() != self.n:
+        if rows and y.dim() == 2 and y.shape[0] > 1:
+            if y.shape != (theta.shape[0], self.n):
+                raise ValueError("y rows %s do not match %d parameter rows x %d locations"
+                                 % (tuple(y.shape), theta.shape[0], self.n))
+        elif y.numel() != self.n:
             raise ValueError("y has %d entries, plan has %d locations" % (y.numel(), self.n))
         if theta.shape[0] > self.max_theta:
             raise ValueError("%d parameter vectors exceed max_theta=%d" % (theta.shape[0], self.max_theta))
@@ -171,15 +177,17 @@ class Plan:
     def loglik_grad_data(self, y, theta, out=None):
         """(loglik [n_theta], grad [n_theta, 3], grad_y [n_theta, n]), where
         grad_y = d loglik / d y = -Sigma^{-1} y in the caller's order, from
-        the same reverse pass; out = (loglik, grad, grad_y) optionally names
-        the output tensors."""
-        y, theta = self._prep(y, theta)
+        the same reverse pass.  y is one data vector (n,) for all parameter
+        rows, or (n_theta, n): one data vector per row.  out = (loglik, grad,
+        grad_y) optionally names the output tensors."""
+        y, theta = self._prep(y, theta, rows=True)
+        stride = self.n if y.dim() == 2 and y.shape[0] > 1 else 0
         out, g, gy = (None, None, None) if out is None else out
         out = self._out(out, (theta.shape[0],))
         g = self._out(g, (theta.shape[0], 3))
         gy = self._out(gy, (theta.shape[0], self.n))
-        s = _lib.lib().mra_loglik_grad_data(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0], out.data_ptr(),
-                                            g.data_ptr(), gy.data_ptr(), self._stream())
+        s = _lib.lib().mra_loglik_grad_data(self._h, y.data_ptr(), stride, theta.data_ptr(), theta.shape[0],
+                                            out.data_ptr(), g.data_ptr(), gy.data_ptr(), self._stream())
         self._fail(s, "mra_loglik_grad_data")
         return out, g, gy
 
@@ -192,11 +200,12 @@ class Plan:
         maximises the likelihood for every theta).
 
         Sigma^{-1} X comes from the library's data gradient (one
-        mra_loglik_grad_data call per column of X), the profile likelihood
-        from one mra_loglik_grad call at the residual; the p x p normal
-        equations, their right-hand side and the residual are host
-        arithmetic on those results.  Returns a dict with beta (p,),
-        loglik, grad (3,) and XtSiX (p, p)."""
+        mra_loglik_grad_data call with a data row per column of X, in
+        batches of max_theta), the profile likelihood from one
+        mra_loglik_grad call at the residual; the p x p normal equations,
+        their right-hand side and the residual are host arithmetic on those
+        results.  Returns a dict with beta (p,), loglik, grad (3,) and
+        XtSiX (p, p)."""
         torch = _torch()
 
         def host(a):
@@ -206,9 +215,11 @@ class Plan:
         Xh = np.ascontiguousarray(host(X), dtype=np.float64).reshape(yh.shape[0], -1)
         th = np.asarray(host(theta), dtype=np.float64).reshape(1, 3)
         SiX = np.empty_like(Xh)
-        for j in range(Xh.shape[1]):
-            _, _, gy = self.loglik_grad_data(np.ascontiguousarray(Xh[:, j]), th)
-            SiX[:, j] = -gy[0].cpu().numpy()
+        for j0 in range(0, Xh.shape[1], self.max_theta):
+            j1 = min(j0 + self.max_theta, Xh.shape[1])
+            rows = np.ascontiguousarray(Xh[:, j0:j1].T)
+            _, _, gy = self.loglik_grad_data(rows if j1 - j0 > 1 else rows[0], np.repeat(th, j1 - j0, axis=0))
+            SiX[:, j0:j1] = -gy.cpu().numpy().T
         A = Xh.T @ SiX
         beta = np.linalg.solve(A, SiX.T @ yh)
         ll, g = self.loglik_grad(yh - Xh @ beta, th)

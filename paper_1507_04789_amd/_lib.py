@@ -59,7 +59,7 @@ def lib() -> C.CDLL:
     L.mra_bind.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
     L.mra_loglik.argtypes = [vp, vp, vp, i32, vp, vp]
     L.mra_loglik_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
-    L.mra_loglik_grad_data.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    L.mra_loglik_grad_data.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, vp]
     L.mra_predict.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mra_last_failure.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp]
     L.mra_profile.argtypes = [vp, i32]

@@ -86,9 +86,11 @@ struct GraphKey {
   int kind;  // 0 loglik, 1 loglik + grad, 2 predict
   int nth;
   const void* p[5];
+  int64_t y_stride = 0;
   bool operator<(const GraphKey& o) const {
     if (kind != o.kind) return kind < o.kind;
     if (nth != o.nth) return nth < o.nth;
+    if (y_stride != o.y_stride) return y_stride < o.y_stride;
     for (int i = 0; i < 5; ++i)
       if (p[i] != o.p[i]) return p[i] < o.p[i];
     return false;
@@ -139,13 +141,13 @@ hipError_t run_call(mra_plan_s* H, const GraphKey& key, hipStream_t st, F enqueu
 }
 
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
-                           double* gy, hipStream_t st) {
+                           double* gy, hipStream_t st, int64_t y_stride = 0) {
   const bool overlap = !(H->cfg.flags & MRA_PLAIN);
   hipError_t e;
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
   const Side sd = side_of(H);
   const Side* side = overlap ? &sd : nullptr;
-  if ((e = launch_forward_front(*H, y, theta, nth, st, side)) != hipSuccess) return e;
+  if ((e = launch_forward_front(*H, y, theta, nth, st, side, y_stride)) != hipSuccess) return e;
   const bool on_side = side && H->side_solves > 0;
   if (!on_side) {
     if (side && H->nbig() > 0 && (e = hipStreamWaitEvent(st, sd.big, 0)) != hipSuccess) return e;   // every leaf
@@ -376,18 +378,19 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
 }
 
 namespace {
-mra_status loglik_grad_call(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta,
-                            double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
+mra_status loglik_grad_call(mra_plan_t P, const double* d_y, int64_t y_stride, const double* d_theta,
+                            int32_t n_theta, double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
   mra_status s = check_call(P, n_theta);
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
+  if (y_stride != 0 && y_stride < P->n) return MRA_EINVAL;
   if (P->cfg.flags & MRA_NO_GRAD) return MRA_ESTATE;
   hipStream_t st = (hipStream_t)stream;
   P->last_nth = n_theta;
   if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
-  const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, d_grad_y}};
+  const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, d_grad_y}, y_stride};
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
-    return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, q);
+    return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, q, y_stride);
   }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
@@ -397,13 +400,13 @@ mra_status loglik_grad_call(mra_plan_t P, const double* d_y, const double* d_the
 
 mra_status mra_loglik_grad(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta, double* d_loglik,
                            double* d_grad, void* stream) {
-  return loglik_grad_call(P, d_y, d_theta, n_theta, d_loglik, d_grad, nullptr, stream);
+  return loglik_grad_call(P, d_y, 0, d_theta, n_theta, d_loglik, d_grad, nullptr, stream);
 }
 
-mra_status mra_loglik_grad_data(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta,
-                                double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
+mra_status mra_loglik_grad_data(mra_plan_t P, const double* d_y, int64_t y_stride, const double* d_theta,
+                                int32_t n_theta, double* d_loglik, double* d_grad, double* d_grad_y, void* stream) {
   if (!d_grad_y) return MRA_EINVAL;
-  return loglik_grad_call(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, stream);
+  return loglik_grad_call(P, d_y, y_stride, d_theta, n_theta, d_loglik, d_grad, d_grad_y, stream);
 }
 
 mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_var,

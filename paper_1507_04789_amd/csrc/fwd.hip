@@ -27,9 +27,11 @@ __global__ void k_init(DevPlan P) {
   if (blockIdx.x == 0 && threadIdx.x < 4) S[P.off_status + threadIdx.x] = 0.0;
 }
 
-// plane M of the leaf rows: z in column 0 (leaf order, padded), zero elsewhere
-__global__ void k_gather(DevPlan P, const double* y) {
+// plane M of the leaf rows: z in column 0 (leaf order, padded), zero elsewhere;
+// parameter row b reads its data at y + b * y_stride
+__global__ void k_gather(DevPlan P, const double* y, int64_t y_stride) {
   double* S = slice(P, blockIdx.y);
+  y += blockIdx.y * y_stride;
   double* zp = S + P.off_wobs + (int64_t)P.M * P.plane;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < P.plane; e += (int64_t)gridDim.x * NT) {
     int64_t p = e >> 6;
@@ -400,7 +402,7 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 // leaves proceed on `st`; side->big marks their completion and is awaited in
 // launch_forward_back.
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                const Side* side) {
+                                const Side* side, int64_t y_stride) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -408,7 +410,7 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   int64_t gx = (P.plane + NT - 1) / NT;
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride);
   for (int m = 0; m < M; ++m)
     run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, H.nact_prior(m), theta, m);
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,

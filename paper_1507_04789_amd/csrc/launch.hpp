@@ -181,8 +181,9 @@ struct Side {
   hipStream_t s;
   hipEvent_t fork, big, fork2, join, join2;   // join: V done; join2: L^{-1} done
 };
+// y_stride: parameter row b uses the data y + b * y_stride (0: the same data for all rows)
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                const Side* side = nullptr);
+                                const Side* side = nullptr, int64_t y_stride = 0);
 // A callback run once, when the launches of its stage have been enqueued on
 // the main stream: 0 before the leaf reduction, 1 after it, 1 + j after
 // posterior level M - j (and its child sums), j = 1..M, then M + 2 + m after

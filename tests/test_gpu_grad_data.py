@@ -127,9 +127,13 @@ def test_data_grad_rejects_null_and_no_grad_plan():
     th = torch.tensor(_th(1.0, 0.1, 0.05)[None], device="cuda:0")
     ll = torch.empty(1, dtype=torch.float64, device="cuda:0")
     gr = torch.empty(1, 3, dtype=torch.float64, device="cuda:0")
-    s = _lib.lib().mra_loglik_grad_data(p._h, z.data_ptr(), th.data_ptr(), 1, ll.data_ptr(), gr.data_ptr(), None,
+    gy = torch.empty(1, 500, dtype=torch.float64, device="cuda:0")
+    s = _lib.lib().mra_loglik_grad_data(p._h, z.data_ptr(), 0, th.data_ptr(), 1, ll.data_ptr(), gr.data_ptr(), None,
                                         p._stream())
-    assert s == -1   # MRA_EINVAL
+    assert s == -1   # MRA_EINVAL: no data-gradient output
+    s = _lib.lib().mra_loglik_grad_data(p._h, z.data_ptr(), 499, th.data_ptr(), 1, ll.data_ptr(), gr.data_ptr(),
+                                        gy.data_ptr(), p._stream())
+    assert s == -1   # MRA_EINVAL: overlapping data rows
     q = Plan(locs, M=2, J=4, r=9, cov="matern32", flags=MRA_SYNC | MRA_NO_GRAD)
     with pytest.raises(MRAError):
         q.loglik_grad_data(z, th)
@@ -234,3 +238,25 @@ def test_gls_full_size_normal_equations():
         assert ll <= out["loglik"]
     del p
     torch.cuda.empty_cache()
+
+
+def test_data_rows_batch_matches_single_calls():
+    """One call with a data vector per parameter row (y_stride = n) gives,
+    row by row, the same bits as separate single-row calls; GLS with its
+    trend columns batched equals GLS one column per call."""
+    g = np.random.default_rng(50)
+    n = 2000
+    locs = g.random((n, 2))
+    Y = g.standard_normal((3, n))
+    ths = np.stack([_th(0.9, 0.15, 0.03), _th(1.2, 0.1, 0.05), _th(0.7, 0.2, 0.02)])
+    print("data-rows batch n=%d, 3 rows" % n, flush=True)
+    pb = Plan(locs, M=3, J=4, r=16, cov="matern32", max_theta=3)
+    ll, gr, gy = pb.loglik_grad_data(Y, ths)
+    for b in range(3):
+        l1, g1, y1 = pb.loglik_grad_data(Y[b], ths[b])
+        assert torch.equal(ll[b:b + 1], l1) and torch.equal(gr[b:b + 1], g1) and torch.equal(gy[b:b + 1], y1), b
+    X = _trend(locs)
+    z = Y[0] + X @ np.array([0.5, 1.0, -1.0])
+    p1 = Plan(locs, M=3, J=4, r=16, cov="matern32", max_theta=1)
+    a, b = pb.gls(z, X, ths[0]), p1.gls(z, X, ths[0])
+    assert np.array_equal(a["beta"], b["beta"]) and a["loglik"] == b["loglik"]
