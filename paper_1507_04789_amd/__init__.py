@@ -327,11 +327,19 @@ def _make_autograd():
     class MRALogLik(torch.autograd.Function):
         """loglik(theta) with the library's reverse-pass gradient.
 
-        forward(theta [n_theta, 3], plan, y) -> loglik [n_theta]; when y
-        requires grad, its gradient comes from the same reverse pass."""
+        forward(theta [n_theta, 3], plan, y) -> loglik [n_theta]; y is one
+        data vector (n,) shared by every parameter row, or (n_theta, n) with
+        one data vector per row.  When y requires grad, its gradient comes
+        from the same reverse pass: for a shared y the rows' gradients are
+        summed (loglik[b] depends on y through every row), for per-row data
+        row b's gradient goes to y[b] alone."""
 
         @staticmethod
         def forward(ctx, theta, plan, y):
+            per_row = y.dim() == 2 and y.shape[0] > 1
+            if per_row and not ctx.needs_input_grad[2]:
+                raise ValueError("per-row data (n_theta, n) goes through the data-gradient call; "
+                                 "give y requires_grad=True or pass one data vector")
             if ctx.needs_input_grad[2]:
                 ll, g, gy = plan.loglik_grad_data(y.detach(), theta.detach())
             else:
@@ -339,6 +347,8 @@ def _make_autograd():
             ctx.save_for_backward(g, gy)
             ctx.theta_device = theta.device
             ctx.y_device = y.device
+            ctx.y_shape = tuple(y.shape)
+            ctx.per_row = per_row
             return ll
 
         @staticmethod
@@ -346,7 +356,10 @@ def _make_autograd():
             g, gy = ctx.saved_tensors
             go = gout.to(g.device)
             dtheta = (go[:, None] * g).to(ctx.theta_device)
-            dy = None if gy is None else (go @ gy).to(ctx.y_device)
+            dy = None
+            if gy is not None:
+                dy = go[:, None] * gy if ctx.per_row else go @ gy
+                dy = dy.reshape(ctx.y_shape).to(ctx.y_device)
             return dtheta, None, dy
 
     return MRALogLik

@@ -117,6 +117,32 @@ def test_data_grad_batch_graph_and_autograd():
     np.testing.assert_allclose(yv.grad.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+def test_autograd_per_row_data():
+    """MRALogLik with one data vector per parameter row: y of shape (k, n)
+    with requires_grad receives row b's data gradient (scaled by the
+    incoming weight of loglik[b]) in row b, and theta its usual gradient."""
+    from oracle import mra
+    g = np.random.default_rng(24)
+    locs = g.random((800, 2))
+    Y = g.standard_normal((3, 800))
+    ths = np.stack([_th(1.0, 0.1, 0.05), _th(0.7, 0.2, 0.02), _th(1.3, 0.05, 0.1)])
+    print("autograd per-row data n=800 M=2 r=16, 3 rows", flush=True)
+    p = Plan(locs, M=2, J=4, r=16, cov="matern32", max_theta=3)
+    yv = torch.tensor(Y, device="cuda:0", requires_grad=True)
+    tv = torch.tensor(ths, device="cuda:0", requires_grad=True)
+    ll = MRALogLik.apply(tv, p, yv)
+    wts = np.array([1.0, -2.0, 0.5])
+    (ll * torch.tensor(wts, device="cuda:0")).sum().backward()
+    assert tuple(yv.grad.shape) == (3, 800)
+    geo = Geometry(locs, 2, 2, 4, 16)
+    for b in range(3):
+        _check(yv.grad[b].cpu().numpy(), wts[b] * predict.data_gradient(geo, Y[b], "matern32", ths[b]))
+        rll, rg, _ = mra.loglik(geo, Y[b], "matern32", ths[b], grad=True)
+        assert abs(float(ll[b]) - rll) <= 1e-10 * abs(rll)
+        gt = tv.grad[b].cpu().numpy()
+        assert (np.abs(gt - wts[b] * rg) <= 1e-6 * np.abs(wts[b] * rg)).all(), (gt, wts[b] * rg)
+
+
 def test_data_grad_rejects_null_and_no_grad_plan():
     from paper_1507_04789_amd import MRA_NO_GRAD, _lib
     g = np.random.default_rng(23)
