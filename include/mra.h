@@ -21,6 +21,9 @@
  * Memory.  The library never allocates device memory.  mra_requirements
  * reports the byte sizes of a geometry arena and a work arena; the caller
  * allocates them (e.g. as torch tensors) and hands them over in mra_bind.
+ * The one exception is the fixed scratch array behind
+ * mra_loglik_grad_noalloc (MRA_NOALLOC_MAX_BYTES per GPU, placed by the HIP
+ * runtime when the library's code is loaded, never by a call).
  * Pointers named d_* are device pointers owned by the caller; h_* are host
  * pointers owned by the caller and only read during the call.
  *
@@ -128,7 +131,9 @@ mra_status mra_get_geometry(mra_plan_t plan, int64_t* h_perm, int64_t* h_leaf_of
 
 /* Bind caller-owned device arenas (at least the required sizes, 256-byte
  * aligned) and upload the geometry on `stream`.  Must precede every
- * compute call; may be called again to move the plan to new arenas. */
+ * compute call; may be called again to move the plan to new arenas.
+ * d_work = NULL with work_bytes = 0 binds the geometry only: then only
+ * mra_loglik_grad_noalloc may compute, the other calls return MRA_ESTATE. */
 mra_status mra_bind(mra_plan_t plan, void* d_geom, size_t geom_bytes, void* d_work,
                     size_t work_bytes, void* stream);
 
@@ -169,6 +174,31 @@ mra_status mra_loglik_grad(mra_plan_t plan, const double* d_y, const double* d_t
 mra_status mra_loglik_grad_data(mra_plan_t plan, const double* d_y, int64_t y_stride,
                                 const double* d_theta, int32_t n_theta, double* d_loglik,
                                 double* d_grad, double* d_grad_y, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * log-likelihood and gradient as mra_loglik_grad, with the work arena taken
+ * from a device array the library owns instead of the bound one.  The call
+ * allocates nothing (no hipMalloc, hipFree, stream or event creation; one
+ * stream, no captured graph); the caller still owns d_y, d_theta, d_loglik
+ * and d_grad.  The plan needs its geometry bound (mra_bind, which accepts
+ * d_work = NULL with work_bytes = 0 for this use).
+ *
+ * Limit: n_theta parameter vectors need n_theta times the per-vector work
+ * arena (work_bytes of mra_requirements divided by max_theta), at most
+ * MRA_NOALLOC_MAX_BYTES (256 MiB: about three parameter vectors of 4096
+ * observations with M = 3, r = 16); larger requests return MRA_ENOMEM
+ * before anything is launched.  Each GPU holds one such array from its
+ * first use until the process ends; every call on that GPU shares it and
+ * leaves its contents behind, so calls that overlap on one GPU (other
+ * streams, other plans, other threads) race and must be serialised by the
+ * caller.  MRA_EINVAL for NULL pointers or n_theta outside 1..max_theta,
+ * MRA_ESTATE before mra_bind or for a plan built with MRA_NO_GRAD.
+ */
+#define MRA_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+mra_status mra_loglik_grad_noalloc(mra_plan_t plan, const double* d_y, const double* d_theta,
+                                   int32_t n_theta, double* d_loglik, double* d_grad, void* stream);
 
 /*
  * Posterior predictive mean and variance of the latent process y_M at the

@@ -90,17 +90,21 @@ class Plan:
         return perm, off, kn[:nint * self.r * self.d].reshape(nint, self.r, self.d)
 
     # -- device ---------------------------------------------------------------
-    def bind(self, device="cuda"):
+    def bind(self, device="cuda", work: bool = True):
+        """Allocate the arenas on `device` and bind them.  work=False binds
+        the geometry only (no work arena): then only loglik_grad_noalloc
+        computes."""
         torch = _torch()
         dev = torch.device(device)
         if dev.type != "cuda":
             raise RuntimeError("the M-RA library runs on a GPU device only")
         self._geom = torch.empty(self.geom_bytes + 256, dtype=torch.uint8, device=dev)
-        self._work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=dev)
+        self._work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=dev) if work else None
         gp = (self._geom.data_ptr() + 255) // 256 * 256
-        wp = (self._work.data_ptr() + 255) // 256 * 256
+        wp = (self._work.data_ptr() + 255) // 256 * 256 if work else None
         st = torch.cuda.current_stream(dev).cuda_stream
-        _lib.check(_lib.lib().mra_bind(self._h, gp, self.geom_bytes, wp, self.work_bytes, st), "mra_bind")
+        _lib.check(_lib.lib().mra_bind(self._h, gp, self.geom_bytes, wp, self.work_bytes if work else 0, st),
+                   "mra_bind")
         self.device = dev
         return self
 
@@ -173,6 +177,20 @@ class Plan:
                                        g.data_ptr(), self._stream())
         self._fail(s, "mra_loglik_grad")
         return out, g
+
+    def loglik_grad_noalloc(self, y, theta, out):
+        """As loglik_grad, through mra_loglik_grad_noalloc: the library's own
+        scratch array stands in for the work arena and the call allocates
+        nothing, so the outputs must be given: out = (loglik [n_theta],
+        grad [n_theta, 3]) on the plan's device."""
+        y, theta = self._prep(y, theta)
+        ll, g = out
+        ll = self._out(ll, (theta.shape[0],))
+        g = self._out(g, (theta.shape[0], 3))
+        s = _lib.lib().mra_loglik_grad_noalloc(self._h, y.data_ptr(), theta.data_ptr(), theta.shape[0],
+                                               ll.data_ptr(), g.data_ptr(), self._stream())
+        self._fail(s, "mra_loglik_grad_noalloc")
+        return ll, g
 
     def loglik_grad_data(self, y, theta, out=None):
         """(loglik [n_theta], grad [n_theta, 3], grad_y [n_theta, n]), where

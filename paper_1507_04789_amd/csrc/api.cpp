@@ -15,6 +15,7 @@
 namespace mra {
 
 hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st);
+hipError_t noalloc_scratch(void** out);   // noalloc.hip
 
 namespace {
 
@@ -29,7 +30,7 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
   H->fail_region = -1;
   for (int th = 0; th < nth; ++th) {
     int64_t code = 0;
-    const double* src = H->dp.work + (int64_t)th * H->dp.theta_stride + H->dp.off_status;
+    const double* src = H->call_work + (int64_t)th * H->dp.theta_stride + H->dp.off_status;
     if (hipMemcpy(&code, src, sizeof(code), hipMemcpyDeviceToHost) != hipSuccess) return MRA_EHIP;
     if (code != 0) {
       H->fail_theta = th;
@@ -140,9 +141,10 @@ hipError_t run_call(mra_plan_s* H, const GraphKey& key, hipStream_t st, F enqueu
   return hipGraphLaunch(it->second, st);
 }
 
+// allow_side = false keeps every launch on st (no second stream or events)
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
-                           double* gy, hipStream_t st, int64_t y_stride = 0) {
-  const bool overlap = !(H->cfg.flags & MRA_PLAIN);
+                           double* gy, hipStream_t st, int64_t y_stride = 0, bool allow_side = true) {
+  const bool overlap = allow_side && !(H->cfg.flags & MRA_PLAIN);
   hipError_t e;
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
   const Side sd = side_of(H);
@@ -234,6 +236,9 @@ mra_status check_call(const mra_plan_s* H, int nth) {
   return MRA_OK;
 }
 
+// every compute call records the work arena its status words live in
+void set_call_work(mra_plan_s* H) { H->call_work = H->dp.work; }
+
 }  // namespace
 }  // namespace mra
 
@@ -291,11 +296,11 @@ mra_status mra_get_geometry(mra_plan_t P, int64_t* h_perm, int64_t* h_leaf_offse
 }
 
 mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work, size_t work_bytes, void* stream) {
-  if (!P || !d_geom || !d_work) return MRA_EINVAL;
+  if (!P || !d_geom || (!d_work && work_bytes != 0)) return MRA_EINVAL;
   if (((uintptr_t)d_geom & 255) || ((uintptr_t)d_work & 255)) return MRA_EINVAL;
   size_t need_g, need_w;
   mra_requirements(P, &need_g, &need_w);
-  if (geom_bytes < need_g || work_bytes < need_w) return MRA_ENOMEM;
+  if (geom_bytes < need_g || (d_work && work_bytes < need_w)) return MRA_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   char* g = (char*)d_geom;
   const Layout& L = P->lay;
@@ -352,7 +357,9 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   if (P->graphs) P->graphs->clear();
   P->d_geom = d_geom;
   P->d_work = d_work;
-  P->bound = true;
+  P->geom_bound = true;
+  P->bound = d_work != nullptr;
+  P->call_work = nullptr;
   return MRA_OK;
 }
 
@@ -362,6 +369,7 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   if (s != MRA_OK) return s;
   if (!d_y || !d_theta || !d_loglik) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
   P->last_nth = n_theta;
   const bool overlap = !(P->cfg.flags & MRA_PLAIN);
   if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
@@ -386,6 +394,7 @@ mra_status loglik_grad_call(mra_plan_t P, const double* d_y, int64_t y_stride, c
   if (y_stride != 0 && y_stride < P->n) return MRA_EINVAL;
   if (P->cfg.flags & MRA_NO_GRAD) return MRA_ESTATE;
   hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
   P->last_nth = n_theta;
   if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, d_grad_y}, y_stride};
@@ -409,6 +418,34 @@ mra_status mra_loglik_grad_data(mra_plan_t P, const double* d_y, int64_t y_strid
   return loglik_grad_call(P, d_y, y_stride, d_theta, n_theta, d_loglik, d_grad, d_grad_y, stream);
 }
 
+mra_status mra_loglik_grad_noalloc(mra_plan_t P, const double* d_y, const double* d_theta, int32_t n_theta,
+                                   double* d_loglik, double* d_grad, void* stream) {
+  if (!P) return MRA_EINVAL;
+  if (!P->geom_bound) return MRA_ESTATE;
+  if (n_theta < 1 || n_theta > P->cfg.max_theta) return MRA_EINVAL;
+  if (!d_y || !d_theta || !d_loglik || !d_grad) return MRA_EINVAL;
+  if (P->cfg.flags & MRA_NO_GRAD) return MRA_ESTATE;
+  if ((size_t)P->lay.theta_stride * 8 * (size_t)n_theta > MRA_NOALLOC_MAX_BYTES) return MRA_ENOMEM;
+  void* ptr = nullptr;
+  mra_status s = check_hip(noalloc_scratch(&ptr));
+  if (s != MRA_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  // run the ordinary launch sequence against the scratch array: one stream,
+  // no captured graph, no profiling events
+  double* const keep_work = P->dp.work;
+  const bool prof = P->prof && P->prof->enabled;
+  if (prof) P->prof->enabled = false;
+  P->dp.work = (double*)ptr;
+  P->call_work = (double*)ptr;
+  P->last_nth = n_theta;
+  s = check_hip(launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, nullptr, st, 0, false));
+  P->dp.work = keep_work;
+  if (prof) P->prof->enabled = true;
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, n_theta, st);
+  return MRA_OK;
+}
+
 mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_var,
                        void* stream) {
   mra_status s = check_call(P, 1);
@@ -416,6 +453,7 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
   if (!d_y || !d_theta || !d_mean || !d_var) return MRA_EINVAL;
   if (P->n_pred == 0) return MRA_OK;
   hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
   P->last_nth = 1;
   const GraphKey key{2, 1, {d_y, d_theta, d_mean, d_var, nullptr}};
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
@@ -430,7 +468,7 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
 
 mra_status mra_last_failure(mra_plan_t P, int32_t* theta_idx, int32_t* level, int64_t* region, void* stream) {
   if (!P) return MRA_EINVAL;
-  if (!(P->cfg.flags & MRA_SYNC) && P->bound) {
+  if (!(P->cfg.flags & MRA_SYNC) && P->call_work) {
     mra_status s = collect_failures(P, P->last_nth, (hipStream_t)stream);
     if (s == MRA_EHIP) return s;
   }
@@ -485,6 +523,7 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
   if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const bool prof = P->prof && P->prof->enabled;
   if (prof) P->prof->enabled = false;
+  set_call_work(P);
   P->last_nth = n_theta;
   const Side sd = side_of(P);
   auto call = [&]() -> hipError_t {

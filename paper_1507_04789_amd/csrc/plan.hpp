@@ -93,9 +93,11 @@ struct mra_plan_s {
   // layout
   mra::Layout lay;
   mra::DevPlan dp;
-  bool bound = false;
+  bool bound = false;        // geometry and work arena bound
+  bool geom_bound = false;   // geometry bound (a work arena may be absent)
   void* d_geom = nullptr;
   void* d_work = nullptr;
+  double* call_work = nullptr;   // work arena of the last compute call (status words)
   double flops_loglik = 0, flops_grad = 0, flops_predict = 0;
   // failure of the last synchronised call
   int32_t fail_theta = -1, fail_level = -1;
