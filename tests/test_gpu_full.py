@@ -69,6 +69,94 @@ def test_full_size_theta_batch(data):
     torch.cuda.empty_cache()
 
 
+SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "clustered_n262144_sweep.json")
+
+
+def _errors(ll, g, pt):
+    rll, rg = pt["loglik"], np.asarray(pt["grad"])
+    return abs(ll - rll) / abs(rll), np.abs(g - rg) / np.abs(rg)
+
+
+def test_full_size_sweep_one_batch(data):
+    """The eight finite-difference points (theta_draws(8, 31)) and the
+    worst-conditioned vectors of the 64-vector batch (the largest range and
+    the smallest nugget of theta_draws(64, 41)) as one batched call at full
+    size, launched as the benchmark launches (captured graph), against the
+    stored oracle values: 1e-10 relative on the log-likelihood, 1e-6 per
+    gradient component."""
+    from paper_1507_04789_amd import MRA_GRAPH
+    w, _ = data
+    with open(SWEEP) as f:
+        sweep = json.load(f)
+    pts = sweep["points"]
+    k = len(pts)
+    print("full-size sweep: n=%d M=%d %d thetas in one captured call" % (len(w.z), w.M, k), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=k, flags=MRA_GRAPH)
+    p.bind("cuda:0")
+    z = torch.tensor(w.z, device="cuda:0")
+    th = torch.tensor([pt["theta"] for pt in pts], dtype=torch.float64, device="cuda:0")
+    ll = torch.empty(k, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(k, 3, dtype=torch.float64, device="cuda:0")
+    p.loglik_grad(z, th, out=(ll, g))
+    p.loglik_grad(z, th, out=(ll, g))     # graph replay
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    worst_l, worst_g = 0.0, np.zeros(3)
+    for i, pt in enumerate(pts):
+        el, eg = _errors(float(ll[i]), g[i], pt)
+        print("  %-40s loglik %.2e grad %s" % (pt["set"], el, np.array2string(eg, precision=2)), flush=True)
+        worst_l, worst_g = max(worst_l, el), np.maximum(worst_g, eg)
+        _check(float(ll[i]), g[i], pt)
+    print("worst: loglik %.2e grad %s" % (worst_l, worst_g), flush=True)
+    del p
+    torch.cuda.empty_cache()
+
+
+def test_full_size_central_differences(data):
+    """Central differences with step h = 1e-5 of the GPU log-likelihood at
+    the eight finite-difference points, against the GPU gradient.  The bar
+    is 1e-6 |g| plus the rounding of the difference quotient, 2 eps_l |l| / h
+    with eps_l = 1e-13 (the size of the log-likelihood's rounding at these
+    sizes: GPU and oracle agree to a few 1e-15 relative at the easy points
+    and the oracle's two child orders to 4e-12 at the worst)."""
+    from paper_1507_04789_amd import MRA_NO_GRAD
+    w, _ = data
+    with open(SWEEP) as f:
+        pts = [pt for pt in json.load(f)["points"] if pt["set"].startswith("finite-difference")]
+    h = 1e-5
+    ths = np.asarray([pt["theta"] for pt in pts])
+    pert = []
+    for t in ths:
+        for a in range(3):
+            for sgn in (1.0, -1.0):
+                q = t.copy()
+                q[a] += sgn * h
+                pert.append(q)
+    pert = np.asarray(pert)
+    B = 16
+    print("full-size central differences: %d points, %d loglik evaluations in batches of %d"
+          % (len(pts), len(pert), B), flush=True)
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=B, flags=MRA_NO_GRAD)
+    p.bind("cuda:0")
+    z = torch.tensor(w.z, device="cuda:0")
+    lls = np.concatenate([p.loglik(z, torch.tensor(pert[i:i + B], device="cuda:0")).cpu().numpy()
+                          for i in range(0, len(pert), B)])
+    del p
+    torch.cuda.empty_cache()
+    q = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=len(pts))
+    q.bind("cuda:0")
+    l0, g = q.loglik_grad(z, torch.tensor(ths, device="cuda:0"))
+    l0, g = l0.cpu().numpy(), g.cpu().numpy()
+    del q
+    torch.cuda.empty_cache()
+    fd = ((lls[0::2] - lls[1::2]) / (2 * h)).reshape(len(pts), 3)
+    slack = 2e-13 * np.abs(l0)[:, None] / h
+    for i in range(len(pts)):
+        print("  theta %s fd %s grad %s rel %s" % (np.round(ths[i], 3), fd[i], g[i],
+                                                  np.array2string(np.abs(fd[i] - g[i]) / np.abs(g[i]), precision=2)),
+              flush=True)
+    assert (np.abs(fd - g) <= 1e-6 * np.abs(g) + slack).all(), (fd - g) / g
+
+
 def test_swath_full_size_properties():
     """Satellite-swath workload at full size (n = 2^22 in 24 strips with
     gaps, M = 9, r = 64, 73% of the leaves empty; 2^20 prediction points in
