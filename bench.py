@@ -38,28 +38,65 @@ def _dominant(stats):
     return ranked
 
 
-def cpu_baseline(sample_n: int, sample_M: int, full_flops: float):
-    """The oracle, single-threaded, on a bounded sample of the same workload
-    family; throughput scaled to the full workload by the algorithmic flop
-    ratio."""
+def _oracle_sample(job):
+    """One oracle loglik + forward-mode gradient on the bounded sample,
+    single-threaded BLAS; returns its wall time (seconds)."""
+    n, M, theta = job
+    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import mra
     from oracle.geometry import Geometry
+    from paper_1507_04789_amd import workloads as wl
+    w = wl.clustered(n=n, M=M)
+    with threadpool_limits(1):
+        geo = Geometry(w.locs, 2, w.M, w.J, w.r)
+        t0 = time.perf_counter()
+        mra.loglik(geo, w.z, w.cov, np.asarray(theta if theta is not None else w.theta), grad=True)
+        return time.perf_counter() - t0
+
+
+def _host_cores():
+    """Cores this process may run on, capped at 16 (one GPU's share of the
+    host on the benchmark machines)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        c = os.cpu_count() or 1
+    return max(1, min(c, 16))
+
+
+def cpu_baseline(sample_n: int, sample_M: int, full_flops: float):
+    """The oracle (loglik + forward-mode gradient), unchanged, on a bounded
+    sample of the same workload family: the clustered generator at
+    n = sample_n with M = sample_M (about 64 observations per leaf, as the
+    full workload).  Two modes: one process with single-threaded BLAS, and
+    C processes (C = the host cores available, at most 16) each evaluating
+    its own parameter vector, the CPU form of the multi-parameter batch.
+    Rates are scaled to the full workload by the ratio of algorithmic flops
+    (sample / full).  Runs before the GPU is touched, so the worker
+    processes fork from a process without a GPU context."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     from paper_1507_04789_amd import Plan
     from paper_1507_04789_amd import workloads as wl
     w = wl.clustered(n=sample_n, M=sample_M)
     sp = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov)
-    with threadpool_limits(1):
-        geo = Geometry(w.locs, 2, w.M, w.J, w.r)
-        t0 = time.perf_counter()
-        mra.loglik(geo, w.z, w.cov, w.theta, grad=True)
-        dt = time.perf_counter() - t0
     ratio = sp.info["flops_grad"] / full_flops
-    return {"value": ratio / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle loglik + forward-mode gradient on the same generator at n=%d, M=%d (64 obs/leaf "
-                      "on average, as the full workload), %.2f s single-threaded, scaled by the algorithmic "
-                      "flop ratio %.4g" % (sample_n, sample_M, dt, ratio),
-            "cpu": _cpu_name()}
+    dt1 = _oracle_sample((sample_n, sample_M, None))
+    cores = _host_cores()
+    ths = wl.theta_draws(cores, 41)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
+        per = list(ex.map(_oracle_sample, [(sample_n, sample_M, list(t)) for t in ths]))
+    wall = time.perf_counter() - t0
+    return {"value": cores * ratio / wall, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle loglik + forward-mode gradient, unchanged, on the clustered generator at n=%d, M=%d "
+                      "(about 64 obs per leaf, as the full workload): %d processes with single-threaded BLAS, one "
+                      "parameter vector each (theta_draws(%d, 41)), %.2f s wall (%.2f-%.2f s per evaluation); "
+                      "rate scaled to n=2^18, M=6 by the algorithmic flop ratio %.4g"
+                      % (sample_n, sample_M, cores, cores, wall, min(per), max(per), ratio),
+            "single_thread": {"value": ratio / dt1, "cores": 1, "sample_s": dt1},
+            "cpu": _cpu_name(), "host_cpus_visible": os.cpu_count()}
 
 
 def _src_digest() -> str:
@@ -69,7 +106,9 @@ def _src_digest() -> str:
     d = os.path.join(ROOT, "paper_1507_04789_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+        # the kernels, their headers and the plan (task lists); not the ABI
+        # glue (api.cpp) or the scratch array of the no-allocation call
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")) and f not in ("api.cpp", "noalloc.hip"):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
@@ -90,6 +129,20 @@ def _stored_traffic(kernel: str):
     if kernel not in vals or vals[kernel][1] != _src_digest():
         return None
     return vals[kernel][0]
+
+
+def _stored_mfma(kernel: str):
+    """(executed FP64 MFMA flops per launch, MFMA busy %) of `kernel` from
+    the committed counter summary, or None when missing or taken on other
+    sources."""
+    path = os.path.join(ROOT, "profiles", PROFILE_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        m = re.match(r"^mfma\s+(\S+)\s+(\S+)\s+(\S+)\s+src\s+(\S+)", line.strip())
+        if m and m.group(1) == kernel and m.group(4) == _src_digest():
+            return float(m.group(2)), float(m.group(3))
+    return None
 
 
 def copy_probe(nbytes: int, reps: int = 3):
@@ -178,7 +231,51 @@ def summarize_profiles(root: str, copy_bytes: int):
     out.append("machine-readable (kernel, HBM bytes per launch, source digest):")
     for name, nd, fb, wb in rows:
         out.append("traffic %s %.6g src %s" % (name, fb + wb, _src_digest()))
+    # executed FP64 MFMA work: derived counters MfmaFlopsF64
+    # (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) and MfmaUtil (busy MFMA cycles over
+    # GPU-active cycles times SIMDs), one pass of their own
+    try:
+        mf = _csv(find("mfma", "counter_collection.csv"))
+    except FileNotFoundError:
+        mf = []
+    if mf:
+        per = {}
+        for r in mf:
+            per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in stats}
+        out.append("")
+        out.append("executed FP64 MFMA per dispatch (MfmaFlopsF64, MfmaUtil), with the kernel-trace average duration:")
+        out.append("%-18s %6s %14s %12s %12s" % ("kernel", "disp", "exec_GFLOP", "exec_TF/s", "mfma_busy%"))
+        mrows = []
+        for k, c in per.items():
+            fl = c.get("MfmaFlopsF64", [0.0])
+            ut = c.get("MfmaUtil", [0.0])
+            e = sum(fl) / len(fl)
+            u = sum(ut) / len(ut)
+            ns = avg_ns.get(_short(k))
+            mrows.append((_short(k), len(fl), e, (e / ns / 1e3) if ns else float("nan"), u))
+        mrows.sort(key=lambda x: -x[2] * x[1])
+        for name, nd, e, tf, u in mrows:
+            out.append("%-18s %6d %14.3f %12.2f %12.2f" % (name, nd, e / 1e9, tf, u))
+        out.append("")
+        out.append("machine-readable (kernel, executed FP64 MFMA flops per launch, MFMA busy %, source digest):")
+        for name, nd, e, tf, u in mrows:
+            out.append("mfma %s %.6g %.4g src %s" % (name, e, u, _src_digest()))
     print("\n".join(out))
+
+
+def _executed(kernel: str, alg_flops: float, avg_ms: float):
+    """Executed FP64 MFMA work of the dominant kernel from the committed
+    counters (padding, zero columns and recomputation included), at the
+    launch duration measured in this run; None when the counters were
+    taken on other sources."""
+    got = _stored_mfma(kernel)
+    if got is None:
+        return None
+    e, busy = got
+    tf = e / (avg_ms * 1e-3) / 1e12
+    return {"flops_per_launch": e, "tflops": tf, "frac": tf / PEAK_FP64_TFLOPS, "mfma_busy_pct": busy,
+            "executed_over_algorithmic": e / alg_flops}
 
 
 def _time_calls(fn, steps, warmup=2):
@@ -340,6 +437,12 @@ def main():
     dev = torch.device("cuda:0")
     w = wl.clustered(n=args.n, M=args.M)
     plan = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=0 if args.eager else MRA_GRAPH)
+    cpu = None
+    if not args.no_cpu:
+        # host-only work first: the oracle's worker processes fork from a
+        # process that has not touched the GPU
+        print("cpu baseline: oracle on the bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(65536, max(args.M - 1, 1), plan.info["flops_grad"])
     plan.bind(dev)
     z = torch.tensor(w.z, device=dev)
     th = torch.tensor(w.theta, device=dev).reshape(1, 3)
@@ -435,7 +538,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": _stored_traffic(dom["name"]), "traffic_unit": "bytes",
-                     "flops_per_launch": per_launch_flops, "avg_launch_ms": avg_ms},
+                     "flops_per_launch": per_launch_flops, "avg_launch_ms": avg_ms,
+                     "executed": _executed(dom["name"], per_launch_flops, avg_ms)},
         "kernels": [{"name": f["name"], "ms_per_step": f["total_ms"] / prof_steps,
                      "tflops": (f["flops"] / (f["total_ms"] * 1e-3) / 1e12) if f["total_ms"] > 0 else None}
                     for f in fam],
@@ -449,8 +553,8 @@ def main():
         "result": {"loglik": llv, "grad": gv},
         "wall_s_timed": wall,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(65536, max(args.M - 1, 1), flops)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
