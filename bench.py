@@ -374,8 +374,11 @@ def swath_config(dev):
     ms_g = _time_calls(lambda: p.loglik_grad(zt, th, out=(ll, g)), 3, warmup=1)
     ms_l = _time_calls(lambda: p.loglik(zt, th, out=ll), 3, warmup=1)
     ms_p = _time_calls(lambda: p.predict(zt, th, out=(mu, var)), 3, warmup=1)
+    from paper_1507_04789_amd import MRA_CHECKPOINT
+    ckpt_bytes = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, pred=w.pred, flags=MRA_CHECKPOINT).work_bytes
     res = {"workload": "swaths_n4194304_matern32_M9_J4_r64_pred1048576",
-           "work_arena_gb": p.work_bytes / 1e9, "generation_s": gen_s,
+           "work_arena_gb": p.work_bytes / 1e9, "work_arena_gb_checkpoint": ckpt_bytes / 1e9,
+           "generation_s": gen_s,
            "loglik_grad_ms": ms_g, "loglik_grad_evals_per_s": 1000.0 / ms_g,
            "loglik_grad_fp64_pct_peak": 100.0 * p.info["flops_grad"] / (ms_g * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
            "loglik_ms": ms_l,
@@ -406,6 +409,8 @@ def main():
     ap.add_argument("--M", type=int, default=6)
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the one-launch-per-task form (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--checkpoint-steps", type=int, default=10,
+                    help="steps of the checkpointed form (MRA_CHECKPOINT; 0: skip)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of captured-graph replays")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workloads (small uniform case, loglik only, 64-vector batch)")
@@ -509,6 +514,26 @@ def main():
         del pplan
         torch.cuda.empty_cache()
 
+    # the checkpointed form (MRA_CHECKPOINT): leaf phase in chunks, leaf
+    # planes recomputed for the reverse pass; same workload, graph replays
+    checkpoint = None
+    if args.checkpoint_steps > 0:
+        from paper_1507_04789_amd import MRA_CHECKPOINT
+        work_stored = plan.work_bytes
+        cplan = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=MRA_CHECKPOINT | (0 if args.eager else MRA_GRAPH))
+        cplan.bind(dev)
+        if tuning is not None:
+            cplan.set_tuning({"families": tuning["families"]})
+        cll = torch.empty(1, dtype=torch.float64, device=dev)
+        cg = torch.empty(1, 3, dtype=torch.float64, device=dev)
+        cms = _time_calls(lambda: cplan.loglik_grad(z, th, out=(cll, cg)), args.checkpoint_steps)
+        checkpoint = {"value": 1000.0 / cms, "ms_per_step": cms, "steps": args.checkpoint_steps,
+                      "work_bytes": cplan.work_bytes, "work_bytes_stored_form": work_stored,
+                      "chunks": 8,
+                      "same_result": bool(float(cll[0]) == llv and cg[0].tolist() == gv)}
+        del cplan
+        torch.cuda.empty_cache()
+
     secondary = None
     if not args.no_secondary:
         del plan
@@ -549,6 +574,7 @@ def main():
                           "note": "eager launches with HIP events around every launch group; source of the "
                                   "kernel table and the roofline"},
         "plain": plain,
+        "checkpoint": checkpoint,
         "secondary": secondary,
         "result": {"loglik": llv, "grad": gv},
         "wall_s_timed": wall,

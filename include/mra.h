@@ -66,6 +66,12 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 #define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
 #define MRA_NO_GRAD 8u  /* mra_loglik and mra_predict only: the work arena leaves out the reverse
                            pass's buffers, and mra_loglik_grad(_data) return MRA_ESTATE */
+#define MRA_CHECKPOINT 16u /* keep the prior blocks (eq. priorw at levels < M) and the leaf
+                           factors, and stream the leaf phase through the tree in chunks of
+                           level-(M-1) subtrees: the basis rows W^_R of the leaves (the
+                           largest blocks of eq. priorw) and their solves exist for one chunk
+                           at a time and are recomputed for the reverse pass and kriging
+                           instead of being stored for all n; same results to rounding */
 
 /* MRA_GRAPH: the first call with a given (call kind, n_theta, pointer
  * arguments) captures its whole launch sequence, both internal streams
@@ -84,7 +90,8 @@ typedef struct {
   double lo[2], hi[2];  /* domain box (only the first d entries are read) */
   int32_t cov;          /* mra_cov */
   int32_t max_theta;    /* largest parameter batch a call may pass (>= 1) */
-  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD */
+  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT */
+  int32_t chunks;       /* MRA_CHECKPOINT: leaf chunks (0: 8; at most the level-(M-1) region count) */
 } mra_config;
 
 typedef struct {

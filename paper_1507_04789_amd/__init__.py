@@ -13,9 +13,9 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import MRA_GRAPH, MRA_NO_GRAD, MRA_PLAIN, MRA_SYNC, MRAError
+from ._lib import MRA_CHECKPOINT, MRA_GRAPH, MRA_NO_GRAD, MRA_PLAIN, MRA_SYNC, MRAError
 
-__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH", "MRA_NO_GRAD"]
+__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH", "MRA_NO_GRAD", "MRA_CHECKPOINT"]
 
 _COV = {"exponential": _lib.MRA_COV_EXPONENTIAL, "matern32": _lib.MRA_COV_MATERN32}
 
@@ -30,13 +30,14 @@ class Plan:
 
     locs: (n, d) float64 observation locations; pred: optional (n_pred, d)
     prediction locations; knots: optional explicit knots, a list over levels
-    m < M of arrays (J^m, r, d).  The geometry is built on the host; device
+    m < M of arrays (J^m, r, d); chunks: leaf chunks of an MRA_CHECKPOINT
+    plan (0: the library's default).  The geometry is built on the host; device
     arenas are allocated with torch and bound on first use (or bind()).
     """
 
     def __init__(self, locs, *, M: int, J: int, r: int, cov: str, d: int | None = None,
                  lo=None, hi=None, pred=None, knots=None, max_theta: int = 1,
-                 flags: int = MRA_SYNC):
+                 flags: int = MRA_SYNC, chunks: int = 0):
         L = _lib.lib()
         locs = np.ascontiguousarray(np.asarray(locs, dtype=np.float64))
         if locs.ndim == 1:
@@ -53,6 +54,7 @@ class Plan:
         cfg.cov = _COV[cov]
         cfg.max_theta = max_theta
         cfg.flags = flags
+        cfg.chunks = chunks
         self.cfg = cfg
         self.cov = cov
         self.max_theta = max_theta

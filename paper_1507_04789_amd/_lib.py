@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libmra.so")
 
 MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EHIP, MRA_ESTATE = 0, -1, -2, -3, -4, -5
 MRA_COV_EXPONENTIAL, MRA_COV_MATERN32 = 0, 1
-MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD = 1, 2, 4, 8
+MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD, MRA_CHECKPOINT = 1, 2, 4, 8, 16
 
 # every symbol the header declares
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",
@@ -22,7 +22,7 @@ NOALLOC_MAX_BYTES = 256 << 20   # MRA_NOALLOC_MAX_BYTES
 class Config(C.Structure):
     _fields_ = [("d", C.c_int32), ("M", C.c_int32), ("J", C.c_int32), ("r", C.c_int32),
                 ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("cov", C.c_int32),
-                ("max_theta", C.c_int32), ("flags", C.c_uint32)]
+                ("max_theta", C.c_int32), ("flags", C.c_uint32), ("chunks", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -14,7 +14,8 @@
 
 namespace mra {
 
-hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st);
+hipError_t launch_predict(const mra_plan_s& H, const double* y, const double* theta, double* mean, double* var,
+                          hipStream_t st);
 hipError_t noalloc_scratch(void** out);   // noalloc.hip
 
 namespace {
@@ -69,6 +70,9 @@ hipError_t ensure_side(mra_plan_s* H) {
   H->ev_join2 = ev[4];
   return hipSuccess;
 }
+
+// the second stream is used by the batched forms without checkpointing
+bool uses_side(const mra_plan_s* H) { return !(H->cfg.flags & MRA_PLAIN) && H->nchunks == 1; }
 
 Side side_of(const mra_plan_s* H) {
   return Side{(hipStream_t)H->side_stream, (hipEvent_t)H->ev_fork, (hipEvent_t)H->ev_big, (hipEvent_t)H->ev_fork2,
@@ -144,7 +148,7 @@ hipError_t run_call(mra_plan_s* H, const GraphKey& key, hipStream_t st, F enqueu
 // allow_side = false keeps every launch on st (no second stream or events)
 hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, int nth, double* ll, double* g,
                            double* gy, hipStream_t st, int64_t y_stride = 0, bool allow_side = true) {
-  const bool overlap = allow_side && !(H->cfg.flags & MRA_PLAIN);
+  const bool overlap = allow_side && uses_side(H);
   hipError_t e;
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
   const Side sd = side_of(H);
@@ -179,7 +183,7 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   if ((e = launch_forward_back(*H, nth, ll, st, side, hk)) != hipSuccess) return e;
   if ((e = launch_grad_post(*H, nth, st, hk)) != hipSuccess) return e;
   if (on_side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
-  return launch_grad_rest(*H, theta, nth, g, gy, st, on_side ? sd.join2 : nullptr);
+  return launch_grad_rest(*H, y, y_stride, theta, nth, g, gy, st, on_side ? sd.join2 : nullptr);
 }
 
 // ---- tuning table (JSON) ----
@@ -371,7 +375,7 @@ mra_status mra_loglik(mra_plan_t P, const double* d_y, const double* d_theta, in
   hipStream_t st = (hipStream_t)stream;
   set_call_work(P);
   P->last_nth = n_theta;
-  const bool overlap = !(P->cfg.flags & MRA_PLAIN);
+  const bool overlap = uses_side(P);
   if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const GraphKey key{0, n_theta, {d_y, d_theta, d_loglik, nullptr, nullptr}};
   const Side sd = side_of(P);
@@ -396,7 +400,7 @@ mra_status loglik_grad_call(mra_plan_t P, const double* d_y, int64_t y_stride, c
   hipStream_t st = (hipStream_t)stream;
   set_call_work(P);
   P->last_nth = n_theta;
-  if (!(P->cfg.flags & MRA_PLAIN) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
+  if (uses_side(P) && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const GraphKey key{1, n_theta, {d_y, d_theta, d_loglik, d_grad, d_grad_y}, y_stride};
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
     return launch_grad_all(P, d_y, d_theta, n_theta, d_loglik, d_grad, d_grad_y, q, y_stride);
@@ -459,7 +463,7 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
   s = check_hip(run_call(P, key, st, [&](hipStream_t q) {
     hipError_t e = launch_forward(*P, d_y, d_theta, 1, nullptr, q);
     if (e != hipSuccess) return e;
-    return launch_predict(*P, d_theta, d_mean, d_var, q);
+    return launch_predict(*P, d_y, d_theta, d_mean, d_var, q);
   }));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
@@ -519,7 +523,7 @@ mra_status mra_autotune(mra_plan_t P, const double* d_y, const double* d_theta, 
   const bool grad = !(P->cfg.flags & MRA_NO_GRAD);
   if (!d_y || !d_theta || !d_loglik || (grad && !d_grad) || reps < 1) return MRA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  const bool overlap = !(P->cfg.flags & MRA_PLAIN);
+  const bool overlap = uses_side(P);
   if (overlap && (s = check_hip(ensure_side(P))) != MRA_OK) return s;
   const bool prof = P->prof && P->prof->enabled;
   if (prof) P->prof->enabled = false;

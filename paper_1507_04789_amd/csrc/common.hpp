@@ -30,16 +30,18 @@ __device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
   l = kl - k * (k + 1) / 2;
 }
 
-// posterior storage of region (m, i)
+// posterior storage of region (m, i): A^{k,l} tiles, w^k, the inverse
+// factor Lt^{-1} of the whitened K~^{-1} = Lt Lt', Z_l = Lt^{-1} A^{m,l},
+// z_w = Lt^{-1} w^m, d and u.  Once the forward pass is done the A tiles are
+// dead, and the reverse pass keeps its subtree sums there (Grad::Tsum).
 struct Post {
   double* base;
   int m;
   __device__ double* A(int k, int l) const { return base + (int64_t)kl_index(k, l) * TT; }
   __device__ double* omega(int k) const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + k * T; }
-  __device__ double* Lt() const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + (m + 1) * T; }
-  __device__ double* Lti() const { return Lt() + TT; }
-  __device__ double* Z(int l) const { return Lt() + 2 * TT + (int64_t)l * TT; }
-  __device__ double* zw() const { return Lt() + 2 * TT + (int64_t)m * TT; }
+  __device__ double* Lti() const { return base + (int64_t)(m + 1) * (m + 2) / 2 * TT + (m + 1) * T; }
+  __device__ double* Z(int l) const { return Lti() + TT + (int64_t)l * TT; }
+  __device__ double* zw() const { return Lti() + TT + (int64_t)m * TT; }
   __device__ double* d() const { return zw() + T; }
   __device__ double* u() const { return zw() + T + 1; }
 };
@@ -82,22 +84,25 @@ __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const doub
 // reverse-pass storage of region (m, i):
 //   G(l), l <= m   cotangent of A^{m,l} of this region (row m of the posterior cotangent)
 //   wbar_omega()   cotangent of w^m
-//   Tsum(l, k)     sum over the subtree's rows of W-bar^l' W^^k, k <= l <= m
 //   Wbar(l), l < m cotangent rows of W^^l, then W-bar^l, of the region's knots
 //   scratch()      one tile
+//   Tsum(l, k)     sum over the subtree's rows of W-bar^l' W^^k, k <= l <= m,
+//                  kept in the region's A tiles (dead after the forward pass)
 struct Grad {
   double* base;
+  double* tbase;   // the region's posterior A tiles
   int m;
-  __device__ int64_t nA() const { return (int64_t)(m + 1) * (m + 2) / 2; }
   __device__ double* G(int l) const { return base + (int64_t)l * TT; }
   __device__ double* wbar_omega() const { return base + (int64_t)(m + 1) * TT; }
-  __device__ double* Tsum(int l, int k) const { return base + (int64_t)(m + 1) * TT + T + (int64_t)kl_index(l, k) * TT; }
-  __device__ double* Wbar(int l) const { return base + (int64_t)(m + 1) * TT + T + nA() * TT + (int64_t)l * TT; }
-  __device__ double* scratch() const { return base + (int64_t)(m + 1) * TT + T + nA() * TT + (int64_t)m * TT; }
+  __device__ double* Wbar(int l) const { return base + (int64_t)(m + 1) * TT + T + (int64_t)l * TT; }
+  __device__ double* scratch() const { return base + (int64_t)(m + 1) * TT + T + (int64_t)m * TT; }
+  __device__ double* Tsum(int l, int k) const { return tbase + (int64_t)kl_index(l, k) * TT; }
 };
 __device__ __forceinline__ Grad grad_of(const DevPlan& P, double* S, int m, int64_t i) {
   Grad g;
-  g.base = S + P.grad_off[m] + (int64_t)P.slot_post[P.reg_base[m] + i] * P.grad_stride[m];
+  const int64_t slot = P.slot_post[P.reg_base[m] + i];
+  g.base = S + P.grad_off[m] + slot * P.grad_stride[m];
+  g.tbase = S + P.post_off[m] + slot * P.post_stride[m];
   g.m = m;
   return g;
 }

@@ -38,6 +38,7 @@ struct DevPlan {
   const int32_t* act_prior;     // active regions (prior), level by level
   const int32_t* act_post;      // active regions (posterior and reverse), level by level
   int64_t n_sig_tasks, n_row_tasks;
+  int64_t n_sig_tiles;       // leaf-factor tiles (nb * nb per leaf)
   const double* pred_xy;     // [ppad][2]
   const int64_t* pred_gidx;  // [ppad]
   const int32_t* pred_tasks; // [n_pred_tasks][2] (leaf, first padded prediction row)
@@ -71,7 +72,9 @@ struct DevPlan {
   int64_t off_sbar;    // Sigma-bar tiles (same layout as off_sig)
   int64_t off_linv;    // tiles of L_Sigma^{-1} (same layout as off_sig)
   int64_t off_wbar;    // M planes: cotangent of the leaf rows of W^ (then W-bar)
-  int64_t off_gpart;   // gradient partial sums, [n_gpart][4]
+  int64_t off_gpart;   // gradient partial sums, [n_gpart][4]: one slot per leaf-factor tile (in leaf
+                       // order), per row tile, per internal region; summed in that order, so the
+                       // result does not depend on how the tasks are ordered or launched
   int64_t n_gpart;
   // prediction
   int64_t off_pw;      // M planes [ppad][T] of U^ rows, then B~ rows

@@ -27,14 +27,15 @@ __global__ void k_init(DevPlan P) {
   if (blockIdx.x == 0 && threadIdx.x < 4) S[P.off_status + threadIdx.x] = 0.0;
 }
 
-// plane M of the leaf rows: z in column 0 (leaf order, padded), zero elsewhere;
-// parameter row b reads its data at y + b * y_stride
-__global__ void k_gather(DevPlan P, const double* y, int64_t y_stride) {
+// plane M of the leaf rows [p_begin, p_end): z in column 0 (leaf order,
+// padded), zero elsewhere; parameter row b reads its data at y + b * y_stride
+__global__ void k_gather(DevPlan P, const double* y, int64_t y_stride, int64_t p_begin, int64_t p_end) {
   double* S = slice(P, blockIdx.y);
   y += blockIdx.y * y_stride;
-  double* zp = S + P.off_wobs + (int64_t)P.M * P.plane;
-  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < P.plane; e += (int64_t)gridDim.x * NT) {
-    int64_t p = e >> 6;
+  double* zp = S + P.off_wobs + (int64_t)P.M * P.plane + p_begin * T;
+  const int64_t ne = (p_end - p_begin) * T;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < ne; e += (int64_t)gridDim.x * NT) {
+    int64_t p = p_begin + (e >> 6);
     int col = (int)(e & 63);
     int64_t g = P.obs_gidx[p];
     zp[e] = (col == 0 && g >= 0) ? y[g] : 0.0;
@@ -286,8 +287,6 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   __syncthreads();
   const bool ok = potrf_trtri(lds, lds_x, po.Lti());
   const double ld = 2.0 * logdiag_lds(lds, T, red);
-  lds_to_global(lds, po.Lt());
-  __syncthreads();
   // Z_l = Lt^{-1} A^{m,l}: the inverse is still in lds_x (pitch PLD)
   Acc acc;
   for (int l = 0; l < m; ++l) {
@@ -396,23 +395,100 @@ __global__ void k_mark_failed(DevPlan P, double* out, int width) {
 }
 
 // ------------------------------------------------------------------ launches
+
+// Device plan for leaf chunk c (MRA_CHECKPOINT): the plane buffers hold only
+// the chunk's rows and the L^{-1} buffer only its leaves' tiles, so their
+// offsets are shifted back by the chunk's first row and first tile; every
+// kernel then addresses them with global row and tile indices.  The whole
+// plan when there is a single chunk.
+DevPlan chunk_plan(const mra_plan_s& H, int c) {
+  DevPlan P = H.dp;
+  if (H.nchunks > 1) {
+    const int64_t sh = H.chunk_row[c] * T;
+    P.off_wobs -= sh;
+    P.off_y -= sh;
+    P.off_v -= sh;
+    P.off_q -= sh;
+    P.off_wbar -= sh;
+    P.off_linv -= H.ck_soff[c] * TT;
+  }
+  return P;
+}
+
+// share of a whole-plan flop count carried by the tasks [a, b) of n
+static double share(double f, int64_t a, int64_t b, int64_t n) { return n > 0 ? f * (double)(b - a) / (double)n : 0.0; }
+
+// data plane of chunk c (z in column 0 of plane M)
+static void gather_chunk(const mra_plan_s& H, const DevPlan& P, int c, const double* y, int64_t y_stride, int nth,
+                         hipStream_t st) {
+  const int64_t p0 = H.chunk_row[c], p1 = H.chunk_row[c + 1];
+  if (p1 <= p0) return;
+  int64_t gx = ((p1 - p0) * T + NT - 1) / NT;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, p0, p1);
+}
+
+// The leaf planes of chunk c: the data plane, the basis rows W^ (eq. priorw
+// at level M) and Y = L_Sigma^{-1} [W^ | z].  With factor = true also the
+// leaf covariances and their factors (forward pass); otherwise the stored
+// factors are used and the work is recomputation (flops not counted).
+hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const double* theta, int nth,
+                              hipStream_t st, int64_t y_stride, bool factor) {
+  const DevPlan P = chunk_plan(H, c);
+  const PhaseFlops& F = H.pf;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  const int64_t nrow = (int64_t)H.row_tasks.size() / 2, nsig = (int64_t)H.sig_tasks.size() / 3;
+  const int64_t nfac = (int64_t)H.fac_tasks.size();
+  gather_chunk(H, P, c, y, y_stride, nth, st);
+  const int64_t r0 = H.ck_row[c], r1 = H.ck_row[c + 1];
+  run.tuned(F_LEAF_ROWS, MAP_CHUNKED, factor ? "leaf_rows" : "leaf_rows_re", -1,
+            factor ? share(F.leaf_rows, r0, r1, nrow) : 0.0, 1, nullptr, k_leaf_rows, r0, r1, theta);
+  const int64_t f0 = H.ck_fac[c], f1 = H.ck_fac[c + 1];
+  if (factor) {
+    run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, share(F.sigma, H.ck_sig[c], H.ck_sig[c + 1], nsig), 1, nullptr,
+              k_sigma, H.ck_sig[c], H.ck_sig[c + 1], theta);
+    run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, H.potrf_flops_big(f1) - H.potrf_flops_big(f0), 1, nullptr,
+              k_leaf_potrf, f0, f1);
+  }
+  run.tuned(F_TRSM, MAP_GROUPED, factor ? "leaf_trsm" : "leaf_trsm_re", -1,
+            factor ? H.trsm_flops_big(f1) - H.trsm_flops_big(f0) : 0.0, M + 1, nullptr, k_leaf_trsm, f0 * (M + 1),
+            f1 * (M + 1));
+  (void)nfac;
+  return hipGetLastError();
+}
+
 // init, prior levels and the leaf factorisation (everything the reverse
 // pass's leaf solves depend on).  With a side stream, the leaves of
 // big_tiles tiles or more are factored and solved there while the small
 // leaves proceed on `st`; side->big marks their completion and is awaited in
-// launch_forward_back.
+// launch_forward_back.  With MRA_CHECKPOINT the leaf phase and the leaf
+// products run chunk by chunk here (no side stream).
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
                                 const Side* side, int64_t y_stride) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
-  int64_t gx = (P.plane + NT - 1) / NT;
-  if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride);
   for (int m = 0; m < M; ++m)
     run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, H.nact_prior(m), theta, m);
+  if (H.nchunks > 1) {
+    const int nkl = M * (M + 1) / 2;
+    const int64_t nred = (int64_t)H.reduce_order.size();
+    for (int c = 0; c < H.nchunks; ++c) {
+      hipError_t e = launch_leaf_planes(H, c, y, theta, nth, st, y_stride, true);
+      if (e != hipSuccess) return e;
+      const DevPlan Pc = chunk_plan(H, c);
+      Runner rc{Pc, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+      rc.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, share(F.leaf_reduce, H.ck_red[c], H.ck_red[c + 1], nred),
+               nkl, nullptr, k_leaf_reduce, H.ck_red[c] * nkl, H.ck_red[c + 1] * nkl);
+    }
+    return hipGetLastError();
+  }
+  int64_t gx = (P.npad * T + NT - 1) / NT;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, (int64_t)0, P.npad);
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,
             (int64_t)H.row_tasks.size() / 2, theta);
   run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, F.sigma, 1, nullptr, k_sigma, 0, (int64_t)H.sig_tasks.size() / 3,
@@ -449,7 +525,16 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
   auto at = [&](int stage) -> hipError_t { return hook ? hook->at(stage) : hipSuccess; };
   hipError_t e = at(0);
   if (e != hipSuccess) return e;
-  if (M == 0) {
+  if (H.nchunks > 1) {   // leaf products already formed chunk by chunk
+    if ((e = at(1)) != hipSuccess) return e;
+    for (int m = M - 1; m >= 0; --m) {
+      run.tuned(F_POST, MAP_IDENTITY, "post", m, F.post[m], 1, nullptr, k_post, 0, H.nact_post(m), m, out_loglik);
+      if (m > 0)
+        run.tuned(F_POST_REDUCE, MAP_GROUPED, "post_reduce", m, F.post_reduce[m], m * (m + 1) / 2, nullptr,
+                  k_post_reduce, 0, H.nact_post(m - 1) * (int64_t)(m * (m + 1) / 2), m);
+      if ((e = at(1 + M - m)) != hipSuccess) return e;
+    }
+  } else if (M == 0) {
     if (split && (e = hipStreamWaitEvent(st, side->big, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_root_leaf, dim3(1, nth), dim3(NT), 0, st, P, out_loglik);
   } else {

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   const double wgt = (bi == bj) ? 1.0 : 2.0;   // lower tiles stand for both triangles
   g[0] *= wgt;
   g[1] *= wgt;
-  write_partial(P, S, tk, g, red);
+  write_partial(P, S, P.leaf_soff[leaf] + (int64_t)bi * nb + bj, g, red);
 }
 
 // Reverse row sweep for 64 rows (points X, nx valid) of a region at level
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(NT, 3) void k_rrows_leaf(DevPlan P, const double* t
   };
   row_sweep_reverse(P, S, c, P.obs_xy + 2 * p0, nx, S + P.off_wbar + p0 * T, P.plane, P.M, leaf, g, lds, init, nb,
                     extra);
-  write_partial(P, S, P.n_sig_tasks + tk, g, red);
+  write_partial(P, S, P.n_sig_tiles + tk, g, red);
 }
 
 // Tsum^{l,k} of a level-(M-1) region: sum over its leaves' rows of Wbar^l' W^^k
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
   __syncthreads();
   row_sweep_reverse(P, S, c, X, P.r, gr.Wbar(0), TT, m, i, g, lds, [&](Acc& acc, int l) { acc_load(acc, gr.Wbar(l), T); },
                     0, [&](int, int) { return Seg{}; });
-  write_partial(P, S, P.n_sig_tasks + P.n_row_tasks + P.reg_base[m] + i, g, red);
+  write_partial(P, S, P.n_sig_tiles + P.n_row_tasks + P.reg_base[m] + i, g, red);
 }
 
 // Tsum of a level-(m-1) region: sum over children (level m) of
@@ -551,6 +551,13 @@ hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st, h
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
+  if (H.nchunks > 1) {   // MRA_CHECKPOINT: chunk by chunk in launch_grad_rest
+    if (after_v) {
+      const hipError_t e = hipEventRecord(after_v, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   run.tuned(F_RLEAF_V, MAP_GROUPED, "rleaf_v", -1, F.rleaf_v, M + 1, nullptr, k_rleaf_v, 0,
             (int64_t)H.trsm_tasks.size() / 2);
@@ -570,7 +577,7 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHo
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
-  const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
+  const int64_t nslot = P.n_sig_tiles + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
   hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
   hipError_t e;
   for (int m = 0; m < M; ++m) {
@@ -581,28 +588,70 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHo
   return hipGetLastError();
 }
 
+// reverse leaf phase of leaf chunk c (MRA_CHECKPOINT), after its planes W^
+// and Y have been recomputed: V = L^{-T} Y, L^{-1}, Q, Sigma-bar, W-bar and
+// the level-(M-1) T-sums of the chunk
+static void grad_leaf_chunk(const mra_plan_s& H, int c, const double* theta, int nth, double* grad_y, hipStream_t st) {
+  const DevPlan P = chunk_plan(H, c);
+  const PhaseFlops& F = H.pf;
+  const int M = P.M;
+  Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  const int64_t nrow = (int64_t)H.row_tasks.size() / 2, nsig = P.n_sig_tasks;
+  const int64_t r0 = H.ck_row[c], r1 = H.ck_row[c + 1];
+  const int64_t f0 = H.ck_fac[c], f1 = H.ck_fac[c + 1];
+  const int64_t nlinv = (int64_t)H.linv_tasks.size() / 2, nfac = (int64_t)H.fac_tasks.size();
+  auto sh = [](double f, int64_t a, int64_t b, int64_t n) { return n > 0 ? f * (double)(b - a) / (double)n : 0.0; };
+  run.tuned(F_RLEAF_V, MAP_GROUPED, "rleaf_v", -1, sh(F.rleaf_v, f0, f1, nfac), M + 1, nullptr, k_rleaf_v,
+            f0 * (M + 1), f1 * (M + 1));
+  run.tuned(F_RLEAF_LINV, MAP_IDENTITY, "rleaf_linv", -1, sh(F.rleaf_linv, H.ck_linv[c], H.ck_linv[c + 1], nlinv), 1,
+            nullptr, k_rleaf_linv, H.ck_linv[c], H.ck_linv[c + 1]);
+  run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, sh(F.rleaf_q, r0, r1, nrow), M + 1, nullptr, k_rleaf_q,
+            r0 * (M + 1), r1 * (M + 1), grad_y);
+  run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, sh(F.rleaf_sbar, H.ck_sig[c], H.ck_sig[c + 1], nsig), 1,
+            nullptr, k_rleaf_sbar, H.ck_sig[c], H.ck_sig[c + 1], theta);
+  run.tuned(F_RROWS, MAP_CHUNKED, "rrows_leaf", -1, sh(F.rrows + F.rleaf_wbar, r0, r1, nrow), 1, nullptr,
+            k_rrows_leaf, r0, r1, theta);
+  const int nkl = M * (M + 1) / 2;
+  const int64_t nq = H.nact_post(M - 1);
+  run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, sh(F.rT_leaf, H.ck_actq[c], H.ck_actq[c + 1], nq), nkl, nullptr,
+            k_rT_leaf, H.ck_actq[c] * nkl, H.ck_actq[c + 1] * nkl);
+}
+
 // the leaf and prior reverse passes and the final sum (after both of the above)
-hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
-                            hipStream_t st, hipEvent_t wait_linv) {
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* y, int64_t y_stride, const double* theta, int nth,
+                            double* out_grad, double* grad_y, hipStream_t st, hipEvent_t wait_linv) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
-  const int64_t nslot = P.n_sig_tasks + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
-  run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1),
-            grad_y);
-  if (wait_linv) {
-    const hipError_t e = hipStreamWaitEvent(st, wait_linv, 0);
-    if (e != hipSuccess) return e;
-  }
-  run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, F.rleaf_sbar, 1, nullptr, k_rleaf_sbar, 0, P.n_sig_tasks,
-            theta);
-  if (M > 0) {
-    run.tuned(F_RROWS, MAP_CHUNKED, "rrows_leaf", -1, F.rrows + F.rleaf_wbar, 1, H.cut_rrows, k_rrows_leaf, 0, nrow,
+  const int64_t nslot = P.n_sig_tiles + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
+  if (H.nchunks > 1) {
+    // MRA_CHECKPOINT: recompute each chunk's W^ and Y from the stored prior
+    // blocks and leaf factors, then run its reverse leaf phase
+    for (int c = 0; c < H.nchunks; ++c) {
+      const hipError_t e = launch_leaf_planes(H, c, y, theta, nth, st, y_stride, false);
+      if (e != hipSuccess) return e;
+      grad_leaf_chunk(H, c, theta, nth, grad_y, st);
+    }
+  } else {
+    run.tuned(F_RLEAF_Q, MAP_CHUNKED, "rleaf_q", -1, F.rleaf_q, M + 1, nullptr, k_rleaf_q, 0, nrow * (M + 1),
+              grad_y);
+    if (wait_linv) {
+      const hipError_t e = hipStreamWaitEvent(st, wait_linv, 0);
+      if (e != hipSuccess) return e;
+    }
+    run.tuned(F_RLEAF_SBAR, MAP_IDENTITY, "rleaf_sbar", -1, F.rleaf_sbar, 1, nullptr, k_rleaf_sbar, 0, P.n_sig_tasks,
               theta);
-    const int nkl = M * (M + 1) / 2;
-    run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, F.rT_leaf, nkl, nullptr, k_rT_leaf, 0, H.nact_post(M - 1) * (int64_t)nkl);
+    if (M > 0) {
+      run.tuned(F_RROWS, MAP_CHUNKED, "rrows_leaf", -1, F.rrows + F.rleaf_wbar, 1, H.cut_rrows, k_rrows_leaf, 0, nrow,
+                theta);
+      const int nkl = M * (M + 1) / 2;
+      run.tuned(F_RT_LEAF, MAP_GROUPED, "rT_leaf", -1, F.rT_leaf, nkl, nullptr, k_rT_leaf, 0,
+                H.nact_post(M - 1) * (int64_t)nkl);
+    }
+  }
+  if (M > 0) {
     for (int m = M - 1; m >= 0; --m) {
       run.tuned(F_RPRIOR, MAP_IDENTITY, "rprior", m, F.rprior[m], 1, nullptr, k_rprior, 0, H.nact_post(m), theta, m);
       if (m > 0)

@@ -209,7 +209,14 @@ hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHo
 // grad_y (may be null): [nth][n] gradient of the log-likelihood with respect
 // to the data, in the caller's order
 // wait_linv (may be null): event to wait for before the first use of L^{-1}
-hipError_t launch_grad_rest(const mra_plan_s& H, const double* theta, int nth, double* out_grad, double* grad_y,
-                            hipStream_t st, hipEvent_t wait_linv = nullptr);
+hipError_t launch_grad_rest(const mra_plan_s& H, const double* y, int64_t y_stride, const double* theta, int nth,
+                            double* out_grad, double* grad_y, hipStream_t st, hipEvent_t wait_linv = nullptr);
+// MRA_CHECKPOINT leaf chunks: the device plan of chunk c (plane and L^{-1}
+// offsets shifted to the chunk's buffers; the whole plan for one chunk), and
+// the chunk's leaf planes (data, W^, Y; with factor also Sigma and its
+// factor, otherwise recomputed from the stored factors)
+DevPlan chunk_plan(const mra_plan_s& H, int c);
+hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const double* theta, int nth,
+                              hipStream_t st, int64_t y_stride, bool factor);
 
 }  // namespace mra

@@ -86,7 +86,8 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   if (!cfg || (!h_locs && n > 0) || n < 1 || n_pred < 0 || (n_pred > 0 && !h_pred)) return MRA_EINVAL;
   const int d = cfg->d, M = cfg->M, J = cfg->J, r = cfg->r;
   if (d < 1 || d > 2 || M < 0 || M >= MAXL || r < 1 || r > T || cfg->max_theta < 1) return MRA_EINVAL;
-  if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD)) return MRA_EINVAL;
+  if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT)) return MRA_EINVAL;
+  if (cfg->chunks < 0) return MRA_EINVAL;
   if (d == 2 && J != 1 && J != 4) return MRA_EINVAL;
   if (d == 1 && (J < 1 || J > 8)) return MRA_EINVAL;
   if (cfg->cov != MRA_COV_EXPONENTIAL && cfg->cov != MRA_COV_MATERN32) return MRA_EINVAL;
@@ -198,16 +199,49 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
       for (int a = 0; a < d; ++a) P->pred_xy[dst * 2 + a] = h_pred[src * d + a];
       P->pred_gidx[dst] = src;
     }
-  // task lists; leaves are visited largest first so that long factorisations start early
+  // leaf chunks (MRA_CHECKPOINT): contiguous runs of level-(M-1) regions
+  // with about equal padded rows; a single chunk otherwise
+  {
+    const int64_t nparent = M > 0 ? P->nreg[M - 1] : 1;
+    const int64_t per = M > 0 ? J : n_leaves;   // leaves per level-(M-1) region
+    int64_t K = 1;
+    if ((cfg->flags & MRA_CHECKPOINT) && M > 0) K = std::min<int64_t>(cfg->chunks > 0 ? cfg->chunks : 8, nparent);
+    P->chunk_leaf.assign(1, 0);
+    const int64_t total = P->leaf_poff[n_leaves];
+    for (int64_t c = 1; c < K; ++c) {
+      const double goal = (double)total * (double)c / (double)K;
+      int64_t q = P->chunk_leaf.back() / per + 1;   // at least one region per chunk
+      while (q < nparent && (double)P->leaf_poff[q * per] < goal) ++q;
+      if (q >= nparent) break;
+      P->chunk_leaf.push_back(q * per);
+    }
+    P->chunk_leaf.push_back(n_leaves);
+    P->nchunks = (int32_t)P->chunk_leaf.size() - 1;
+    P->chunk_row.assign(P->nchunks + 1, 0);
+    P->rows_cap = T;
+    for (int c = 0; c <= P->nchunks; ++c) P->chunk_row[c] = P->leaf_poff[P->chunk_leaf[c]];
+    for (int c = 0; c < P->nchunks; ++c) P->rows_cap = std::max(P->rows_cap, P->chunk_row[c + 1] - P->chunk_row[c]);
+  }
+  std::vector<int32_t> chunk_of(n_leaves, 0);
+  for (int c = 0; c < P->nchunks; ++c)
+    for (int64_t i = P->chunk_leaf[c]; i < P->chunk_leaf[c + 1]; ++i) chunk_of[i] = c;
+  // task lists; within a chunk, leaves are visited largest first so that
+  // long factorisations start early
   std::vector<int32_t> order(n_leaves);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return P->leaf_n[x] > P->leaf_n[y]; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (chunk_of[x] != chunk_of[y]) return chunk_of[x] < chunk_of[y];
+    return P->leaf_n[x] > P->leaf_n[y];
+  });
   P->row_tasks.clear(); P->sig_tasks.clear(); P->fac_tasks.clear(); P->trsm_tasks.clear(); P->linv_tasks.clear();
   P->pred_tasks.clear();
+  P->ck_sig.assign(P->nchunks + 1, 0);
+  P->ck_fac.assign(P->nchunks + 1, 0);
+  P->ck_linv.assign(P->nchunks + 1, 0);
   for (int32_t i : order) {
     int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
     if (nb == 0) continue;
+    const int c1 = chunk_of[i] + 1;
     P->fac_tasks.push_back(i);
     for (int64_t bi = 0; bi < nb; ++bi)
       for (int64_t bj = 0; bj <= bi; ++bj) {
@@ -216,13 +250,24 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     for (int c = 0; c <= M; ++c) { P->trsm_tasks.push_back(i); P->trsm_tasks.push_back(c); }
     // tile columns of L^{-1} with tiles below the diagonal
     for (int64_t j = 0; j + 1 < nb; ++j) { P->linv_tasks.push_back(i); P->linv_tasks.push_back((int32_t)j); }
+    P->ck_sig[c1] = (int64_t)P->sig_tasks.size() / 3;
+    P->ck_fac[c1] = (int64_t)P->fac_tasks.size();
+    P->ck_linv[c1] = (int64_t)P->linv_tasks.size() / 2;
+  }
+  for (int c = 1; c <= P->nchunks; ++c) {   // chunks without tasks
+    P->ck_sig[c] = std::max(P->ck_sig[c], P->ck_sig[c - 1]);
+    P->ck_fac[c] = std::max(P->ck_fac[c], P->ck_fac[c - 1]);
+    P->ck_linv[c] = std::max(P->ck_linv[c], P->ck_linv[c - 1]);
   }
   // row tiles in tree order (leaf index order is depth-first), so that
   // consecutive tasks share ancestors
+  P->ck_row.assign(P->nchunks + 1, 0);
   for (int64_t i = 0; i < n_leaves; ++i) {
     const int64_t nb = (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T;
     for (int64_t t = 0; t < nb; ++t) { P->row_tasks.push_back((int32_t)i); P->row_tasks.push_back((int32_t)(P->leaf_poff[i] + t * T)); }
+    P->ck_row[chunk_of[i] + 1] = (int64_t)P->row_tasks.size() / 2;
   }
+  for (int c = 1; c <= P->nchunks; ++c) P->ck_row[c] = std::max(P->ck_row[c], P->ck_row[c - 1]);
   {
     // a reverse row sweep costs M(M+1)/2 + M ancestor block products plus M
     // per tile of its leaf; cut the tree-ordered list into 8 runs of equal cost
@@ -240,12 +285,15 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     P->cut_rrows[0] = 0;
     P->cut_rrows[8] = (int32_t)nrow;
   }
+  P->ck_pred.assign(P->nchunks + 1, 0);
   for (int64_t i = 0; i < n_leaves; ++i) {
     int64_t nb = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;
     for (int64_t t = 0; t < nb; ++t) {
       P->pred_tasks.push_back((int32_t)i); P->pred_tasks.push_back((int32_t)(P->pleaf_poff[i] + t * T));
     }
+    P->ck_pred[chunk_of[i] + 1] = (int64_t)P->pred_tasks.size() / 2;
   }
+  for (int c = 1; c <= P->nchunks; ++c) P->ck_pred[c] = std::max(P->ck_pred[c], P->ck_pred[c - 1]);
   if (P->npad > INT32_MAX || P->ppad > INT32_MAX) return MRA_EINVAL;
 
   // pruning of regions with nothing below them
@@ -299,12 +347,34 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
         maxnb[q] = std::max<int64_t>(maxnb[q], (P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T);
       }
     P->reduce_order.assign(P->act_post.begin() + P->act_post_off[M - 1], P->act_post.begin() + P->act_post_off[M]);
-    std::stable_sort(P->reduce_order.begin(), P->reduce_order.end(),
-                     [&](int32_t x, int32_t y) { return maxnb[x] < maxnb[y]; });
+    std::stable_sort(P->reduce_order.begin(), P->reduce_order.end(), [&](int32_t x, int32_t y) {
+      const int cx = chunk_of[(int64_t)x * J], cy = chunk_of[(int64_t)y * J];
+      if (cx != cy) return cx < cy;
+      return maxnb[x] < maxnb[y];
+    });
     for (int t = 0; t < 16; ++t)
       for (int32_t q : P->reduce_order)
         if (maxnb[q] < t) ++P->nsmall_thr[t];
   }
+  // per-chunk ranges of the level-(M-1) lists (both in chunk order) and of
+  // the leaf-factor tiles
+  P->ck_red.assign(P->nchunks + 1, 0);
+  P->ck_actq.assign(P->nchunks + 1, 0);
+  if (M > 0) {
+    for (size_t q = 0; q < P->reduce_order.size(); ++q)
+      P->ck_red[chunk_of[(int64_t)P->reduce_order[q] * J] + 1] = (int64_t)q + 1;
+    for (int64_t q = P->act_post_off[M - 1]; q < P->act_post_off[M]; ++q)
+      P->ck_actq[chunk_of[(int64_t)P->act_post[q] * J] + 1] = q - P->act_post_off[M - 1] + 1;
+  }
+  for (int c = 1; c <= P->nchunks; ++c) {
+    P->ck_red[c] = std::max(P->ck_red[c], P->ck_red[c - 1]);
+    P->ck_actq[c] = std::max(P->ck_actq[c], P->ck_actq[c - 1]);
+  }
+  P->ck_soff.assign(P->nchunks + 1, 0);
+  P->soff_cap = 1;
+  for (int c = 0; c < P->nchunks; ++c) P->ck_soff[c] = P->chunk_leaf[c] < n_leaves ? P->leaf_soff[P->chunk_leaf[c]] : soff;
+  P->ck_soff[P->nchunks] = soff;
+  for (int c = 0; c < P->nchunks; ++c) P->soff_cap = std::max(P->soff_cap, P->ck_soff[c + 1] - P->ck_soff[c]);
 
   // ---- geometry arena layout (bytes, 256-aligned) ----
   Layout& L = P->lay;
@@ -339,6 +409,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   D = DevPlan{};
   D.d = d; D.M = M; D.J = J; D.r = r; D.cov = cfg->cov;
   D.n_sig_tasks = (int64_t)P->sig_tasks.size() / 3;
+  D.n_sig_tiles = P->n_sig_tiles;
   D.n_row_tasks = (int64_t)P->row_tasks.size() / 2;
   D.n = n; D.npad = P->npad; D.n_leaves = n_leaves; D.ppad = P->ppad; D.n_pred = n_pred;
   int64_t w = 0;
@@ -350,7 +421,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     D.act_post_off[m] = P->act_post_off[m];
   }
   for (int m = 0; m < M; ++m) D.prior_off[m] = wtake(P->nact_prior(m) * (m + 2) * TT);
-  D.plane = P->npad * T;
+  D.plane = (P->nchunks > 1 ? P->rows_cap : P->npad) * T;
   D.off_wobs = wtake((M + 1) * D.plane);
   D.off_sig = wtake(P->n_sig_tiles * TT);
   D.off_dinv = wtake(P->n_dinv_tiles * TT);
@@ -360,20 +431,20 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   D.off_scal = wtake(16);
   for (int m = 0; m < M; ++m) {
     int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
-    // A tiles, omega, Ltilde, Ltilde^{-1}, Z tiles, z_omega, d, u
-    D.post_stride[m] = round_up(nA * TT + (m + 1) * T + 2 * TT + m * TT + T + 2, 32);
+    // A tiles (the reverse pass's T-sums once the forward pass is done),
+    // omega, Ltilde^{-1}, Z tiles, z_omega, d, u
+    D.post_stride[m] = round_up(nA * TT + (m + 1) * T + TT + m * TT + T + 2, 32);
     D.post_off[m] = wtake(P->nact_post(m) * D.post_stride[m]);
   }
   // reverse pass: per internal region G row tiles (m+1), omega-bar (T),
-  // T-sums ((m+1)(m+2)/2 tiles), W-bar rows (m tiles) and W-bar^m (1 tile)
+  // W-bar rows (m tiles) and W-bar^m (1 tile); the T-sums take the A tiles
   if (!(cfg->flags & MRA_NO_GRAD)) {
     for (int m = 0; m < M; ++m) {
-      int64_t nA = (int64_t)(m + 1) * (m + 2) / 2;
-      D.grad_stride[m] = round_up((m + 1) * TT + T + nA * TT + m * TT + TT, 32);
+      D.grad_stride[m] = round_up((m + 1) * TT + T + m * TT + TT, 32);
       D.grad_off[m] = wtake(P->nact_post(m) * D.grad_stride[m]);
     }
     D.off_v = wtake((M + 1) * D.plane);
-    D.off_linv = wtake(P->n_sig_tiles * TT);
+    D.off_linv = wtake((P->nchunks > 1 ? P->soff_cap : P->n_sig_tiles) * TT);
     // buffers that are dead by the time the reverse pass writes them: Y
     // (last read by the leaf products and by V = L^-T Y, both finished before
     // Q = V Fbar is formed) holds Q, and each W-bar row tile overwrites the Q
@@ -383,7 +454,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     D.off_wbar = D.off_y;
     D.off_sbar = D.off_sig;
     // gradient partial sums: one slot per task of every gradient-producing launch
-    D.n_gpart = (int64_t)P->sig_tasks.size() / 3 + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
+    D.n_gpart = P->n_sig_tiles + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
     D.off_gpart = wtake(D.n_gpart * 4);
   }
   D.off_pw = wtake(std::max(M, 1) * P->ppad * T);

@@ -90,6 +90,16 @@ struct mra_plan_s {
   double potrf_flops_big(int64_t k) const { return fac_flops_pre.empty() ? 0.0 : fac_flops_pre[k]; }
   double trsm_flops_big(int64_t k) const { return trsm_flops_pre.empty() ? 0.0 : trsm_flops_pre[k]; }
   int32_t cut_rrows[9] = {};  // per-XCD chunks of row_tasks balancing the reverse row sweep's cost
+  // MRA_CHECKPOINT: the leaf phase runs in nchunks contiguous runs of
+  // level-(M-1) regions (one run of all leaves otherwise).  Chunk c holds
+  // leaves [chunk_leaf[c], chunk_leaf[c+1]) and padded rows
+  // [chunk_row[c], chunk_row[c+1]); every leaf task list is ordered by chunk,
+  // and ck_*[c] .. ck_*[c+1] is chunk c's range in it.  The leaf planes hold
+  // rows_cap rows (the largest chunk) and L^{-1} ck_soff_cap tiles.
+  int32_t nchunks = 1;
+  std::vector<int64_t> chunk_leaf, chunk_row, ck_row, ck_sig, ck_fac, ck_linv, ck_red, ck_actq, ck_pred, ck_soff;
+  int64_t rows_cap = 0, soff_cap = 0;
+  bool checkpoint() const { return (cfg.flags & MRA_CHECKPOINT) != 0; }
   // layout
   mra::Layout lay;
   mra::DevPlan dp;

@@ -141,11 +141,27 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   }
 }
 
-hipError_t launch_predict(const mra_plan_s& H, const double* theta, double* mean, double* var, hipStream_t st) {
+// after the forward pass; with MRA_CHECKPOINT the leaf planes W^ and Y of
+// each chunk are recomputed (from y) before its prediction tiles
+hipError_t launch_predict(const mra_plan_s& H, const double* y, const double* theta, double* mean, double* var,
+                          hipStream_t st) {
+  const int64_t npt = (int64_t)H.pred_tasks.size() / 2;
+  if (H.nchunks > 1) {
+    for (int c = 0; c < H.nchunks; ++c) {
+      const int64_t t0 = H.ck_pred[c], t1 = H.ck_pred[c + 1];
+      if (t1 <= t0) continue;
+      const hipError_t e = launch_leaf_planes(H, c, y, theta, 1, st, 0, false);
+      if (e != hipSuccess) return e;
+      const DevPlan P = chunk_plan(H, c);
+      Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+      run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, npt ? H.pf.predict * (double)(t1 - t0) / (double)npt : 0.0,
+                1, nullptr, k_predict, t0, t1, theta, mean, var);
+    }
+    return hipGetLastError();
+  }
   const DevPlan& P = H.dp;
   Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
-  run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, H.pf.predict, 1, nullptr, k_predict, 0,
-            (int64_t)H.pred_tasks.size() / 2, theta, mean, var);
+  run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, H.pf.predict, 1, nullptr, k_predict, 0, npt, theta, mean, var);
   return hipGetLastError();
 }
 

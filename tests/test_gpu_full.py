@@ -69,6 +69,36 @@ def test_full_size_theta_batch(data):
     torch.cuda.empty_cache()
 
 
+def test_full_size_checkpoint(data):
+    """MRA_CHECKPOINT at full size: the three stored points as one batched
+    call with the leaf phase streamed in chunks and the leaf planes
+    recomputed for the reverse pass.  The work arena of a parameter vector
+    stays under 4 GB, the results meet the oracle bar and equal the
+    stored-plane form bit for bit."""
+    from paper_1507_04789_amd import MRA_CHECKPOINT
+    w, gold = data
+    k = len(gold["points"])
+    print("full-size checkpoint: n=%d M=%d %d thetas" % (len(w.z), w.M, k), flush=True)
+    z = torch.tensor(w.z, device="cuda:0")
+    th = torch.tensor([pt["theta"] for pt in gold["points"]], dtype=torch.float64, device="cuda:0")
+    p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=k, flags=MRA_CHECKPOINT)
+    assert p.work_bytes / k < 4e9, p.work_bytes / k
+    p.bind("cuda:0")
+    ll, g = p.loglik_grad(z, th)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    del p
+    torch.cuda.empty_cache()
+    q = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, max_theta=k, flags=0)
+    q.bind("cuda:0")
+    l0, g0 = q.loglik_grad(z, th)
+    l0, g0 = l0.cpu().numpy(), g0.cpu().numpy()
+    del q
+    torch.cuda.empty_cache()
+    for i, pt in enumerate(gold["points"]):
+        _check(float(ll[i]), g[i], pt)
+    assert np.array_equal(ll, l0) and np.array_equal(g, g0), (ll - l0, g - g0)
+
+
 SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "clustered_n262144_sweep.json")
 
 
