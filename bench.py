@@ -328,6 +328,21 @@ def secondary_configs(dev, w2, theta_batch):
                                        (PEAK_FP64_TFLOPS * 1e12)}
     del p2
     torch.cuda.empty_cache()
+    # GLS with the linear trend (1, x, y) in one library call, against one
+    # loglik + gradient call on the same plan (both launched eagerly)
+    pg = Plan(w2.locs, M=w2.M, J=w2.J, r=w2.r, cov=w2.cov, flags=0)
+    pg.bind(dev)
+    X = torch.stack([torch.ones(len(w2.z), dtype=torch.float64), torch.tensor(w2.locs[:, 0]),
+                     torch.tensor(w2.locs[:, 1])], dim=1).to(dev)
+    zt = z2 + X @ torch.tensor([0.5, 1.0, -1.0], dtype=torch.float64, device=dev)
+    og = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, 3, dtype=torch.float64, device=dev))
+    ms_gls = _time_calls(lambda: pg.gls(zt, X, t2), 10)
+    ms_lg = _time_calls(lambda: pg.loglik_grad(zt, t2, out=og), 10)
+    beta = pg.gls(zt, X, t2)["beta"].tolist()
+    res["clustered_n262144_gls_trend3"] = {"gls_ms": ms_gls, "loglik_grad_ms_eager": ms_lg,
+                                           "ratio": ms_gls / ms_lg, "beta": beta}
+    del pg
+    torch.cuda.empty_cache()
     ths = torch.tensor(wl.theta_draws(64, 41), device=dev)
     B = max(1, min(theta_batch, 64))
     p4 = Plan(w2.locs, M=w2.M, J=w2.J, r=w2.r, cov=w2.cov, max_theta=B, flags=MRA_GRAPH)

@@ -183,6 +183,32 @@ mra_status mra_loglik_grad_data(mra_plan_t plan, const double* d_y, int64_t y_st
                                 double* d_grad, double* d_grad_y, void* stream);
 
 /*
+ * Generalised least squares for a linear mean trend z = X beta + (M-RA
+ * field with measurement error), at one parameter vector d_theta[3]: the
+ * paper states the model for a zero-mean field (Sec. 2.1) and removes the
+ * mean before the M-RA (Sec. 4.2); this call estimates a linear mean by
+ *   beta = (X' Sigma^{-1} X)^{-1} X' Sigma^{-1} z
+ * and returns the profile log-likelihood loglik(z - X beta) (Sec. 3.3) and
+ * its gradient in (log sigma^2, log kappa, log tau^2), which, beta
+ * maximising the likelihood for every theta, is the gradient at the fixed
+ * residual.  One forward pass carries the p trend columns beside z, one
+ * reverse pass runs at the residual.
+ *   d_y[n]        data (caller's order)
+ *   d_X[p][n]     trend columns, column j at d_X + j * n (caller's order), 1 <= p <= 63
+ *   d_beta[p]     estimate;  d_loglik[1] profile log-likelihood;  d_grad[3]
+ *   d_resid[n]    residual z - X beta (caller's order)
+ *   d_XtSiX[p][p] X' Sigma^{-1} X (may be NULL)
+ * All device memory owned by the caller; outputs must not overlap inputs.
+ * MRA_EINVAL for NULL pointers or p outside 1..63, MRA_ESTATE before
+ * mra_bind or for MRA_NO_GRAD plans.  A singular X' Sigma^{-1} X gives NaN
+ * outputs and, with MRA_SYNC, MRA_ENOTPD with level M + 1 in
+ * mra_last_failure.  Launched eagerly (never captured by MRA_GRAPH).
+ */
+mra_status mra_gls(mra_plan_t plan, const double* d_y, const double* d_X, int32_t p, const double* d_theta,
+                   double* d_beta, double* d_loglik, double* d_grad, double* d_resid, double* d_XtSiX,
+                   void* stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * log-likelihood and gradient as mra_loglik_grad, with the work arena taken

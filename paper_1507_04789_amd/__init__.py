@@ -213,37 +213,32 @@ class Plan:
 
     def gls(self, y, X, theta):
         """Generalised least-squares mean trend for data y = X beta + (M-RA
-        field with measurement error) at one parameter vector theta (3,):
-        beta = (X' Sigma^{-1} X)^{-1} X' Sigma^{-1} y, the profile
-        log-likelihood loglik(y - X beta; theta) and its gradient.  The
-        gradient at the fixed residual is the profile gradient (beta
-        maximises the likelihood for every theta).
-
-        Sigma^{-1} X comes from the library's data gradient (one
-        mra_loglik_grad_data call with a data row per column of X, in
-        batches of max_theta), the profile likelihood from one
-        mra_loglik_grad call at the residual; the p x p normal equations,
-        their right-hand side and the residual are host arithmetic on those
-        results.  Returns a dict with beta (p,), loglik, grad (3,) and
-        XtSiX (p, p)."""
+        field with measurement error) at one parameter vector theta (3,),
+        through mra_gls: beta = (X' Sigma^{-1} X)^{-1} X' Sigma^{-1} y, the
+        profile log-likelihood loglik(y - X beta; theta) and its gradient
+        (the gradient at the fixed residual), from one forward pass that
+        carries the trend columns beside y and one reverse pass.  X is
+        (n, p) with 1 <= p <= 63.  Returns a dict of device tensors: beta
+        (p,), loglik (1,), grad (3,), resid (n,), XtSiX (p, p)."""
         torch = _torch()
-
-        def host(a):
-            return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a)
-
-        yh = np.ascontiguousarray(host(y), dtype=np.float64).reshape(-1)
-        Xh = np.ascontiguousarray(host(X), dtype=np.float64).reshape(yh.shape[0], -1)
-        th = np.asarray(host(theta), dtype=np.float64).reshape(1, 3)
-        SiX = np.empty_like(Xh)
-        for j0 in range(0, Xh.shape[1], self.max_theta):
-            j1 = min(j0 + self.max_theta, Xh.shape[1])
-            rows = np.ascontiguousarray(Xh[:, j0:j1].T)
-            _, _, gy = self.loglik_grad_data(rows if j1 - j0 > 1 else rows[0], np.repeat(th, j1 - j0, axis=0))
-            SiX[:, j0:j1] = -gy.cpu().numpy().T
-        A = Xh.T @ SiX
-        beta = np.linalg.solve(A, SiX.T @ yh)
-        ll, g = self.loglik_grad(yh - Xh @ beta, th)
-        return {"beta": beta, "loglik": float(ll[0]), "grad": g[0].cpu().numpy(), "XtSiX": A}
+        y, theta = self._prep(y, theta)
+        X = torch.as_tensor(X, dtype=torch.float64)
+        if X.dim() == 1:
+            X = X[:, None]
+        if X.shape[0] != self.n:
+            raise ValueError("X has %d rows, plan has %d locations" % (X.shape[0], self.n))
+        p = X.shape[1]
+        Xt = X.to(self.device).t().contiguous()      # [p][n]
+        out = {"beta": torch.empty(p, dtype=torch.float64, device=self.device),
+               "loglik": torch.empty(1, dtype=torch.float64, device=self.device),
+               "grad": torch.empty(3, dtype=torch.float64, device=self.device),
+               "resid": torch.empty(self.n, dtype=torch.float64, device=self.device),
+               "XtSiX": torch.empty(p, p, dtype=torch.float64, device=self.device)}
+        s = _lib.lib().mra_gls(self._h, y.data_ptr(), Xt.data_ptr(), p, theta[:1].data_ptr(),
+                               out["beta"].data_ptr(), out["loglik"].data_ptr(), out["grad"].data_ptr(),
+                               out["resid"].data_ptr(), out["XtSiX"].data_ptr(), self._stream())
+        self._fail(s, "mra_gls")
+        return out
 
     def fit(self, y, theta0, *, batch: int | None = None, **kw):
         """Maximum-likelihood estimate of (log sigma^2, log kappa, log tau^2)

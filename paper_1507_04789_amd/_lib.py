@@ -15,7 +15,7 @@ MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD, MRA_CHECKPOINT = 1, 2, 4, 8, 16
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",
            "mra_loglik_grad", "mra_loglik_grad_data", "mra_predict", "mra_last_failure", "mra_profile", "mra_profile_read",
            "mra_status_string", "mra_destroy", "mra_autotune", "mra_get_tuning", "mra_set_tuning",
-           "mra_loglik_grad_noalloc"]
+           "mra_loglik_grad_noalloc", "mra_gls"]
 NOALLOC_MAX_BYTES = 256 << 20   # MRA_NOALLOC_MAX_BYTES
 
 
@@ -63,6 +63,7 @@ def lib() -> C.CDLL:
     L.mra_loglik_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.mra_loglik_grad_data.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, vp]
     L.mra_loglik_grad_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.mra_gls.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.mra_predict.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mra_last_failure.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp]
     L.mra_profile.argtypes = [vp, i32]

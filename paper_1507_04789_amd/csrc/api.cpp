@@ -450,6 +450,24 @@ mra_status mra_loglik_grad_noalloc(mra_plan_t P, const double* d_y, const double
   return MRA_OK;
 }
 
+mra_status mra_gls(mra_plan_t P, const double* d_y, const double* d_X, int32_t p, const double* d_theta,
+                   double* d_beta, double* d_loglik, double* d_grad, double* d_resid, double* d_XtSiX, void* stream) {
+  mra_status s = check_call(P, 1);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_X || !d_theta || !d_beta || !d_loglik || !d_grad || !d_resid) return MRA_EINVAL;
+  if (p < 1 || p > T - 1) return MRA_EINVAL;
+  if (P->cfg.flags & MRA_NO_GRAD) return MRA_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
+  P->last_nth = 1;
+  const bool prof = P->prof && P->prof->enabled;
+  (void)prof;
+  s = check_hip(launch_gls(*P, d_y, d_X, p, d_theta, d_beta, d_loglik, d_XtSiX, d_grad, d_resid, st));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
+  return MRA_OK;
+}
+
 mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_var,
                        void* stream) {
   mra_status s = check_call(P, 1);

@@ -79,6 +79,10 @@ struct DevPlan {
   // prediction
   int64_t off_pw;      // M planes [ppad][T] of U^ rows, then B~ rows
   int64_t off_pl;      // per prediction tile pl_stride doubles: L^M, then E, tiles
+  // generalised least squares (mra_gls): three tiles for the root region (the
+  // other regions keep their multi-column quantities in their reverse-pass
+  // storage, free until the reverse pass) and a scalar area
+  int64_t off_gls0;
   int64_t pl_stride;
 };
 

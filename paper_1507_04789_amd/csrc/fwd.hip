@@ -28,8 +28,10 @@ __global__ void k_init(DevPlan P) {
 }
 
 // plane M of the leaf rows [p_begin, p_end): z in column 0 (leaf order,
-// padded), zero elsewhere; parameter row b reads its data at y + b * y_stride
-__global__ void k_gather(DevPlan P, const double* y, int64_t y_stride, int64_t p_begin, int64_t p_end) {
+// padded), the trend columns X[j] (caller's order, [px][n]) in columns
+// 1..px, zero elsewhere; parameter row b reads its data at y + b * y_stride
+__global__ void k_gather(DevPlan P, const double* y, int64_t y_stride, int64_t p_begin, int64_t p_end,
+                         const double* X, int px) {
   double* S = slice(P, blockIdx.y);
   y += blockIdx.y * y_stride;
   double* zp = S + P.off_wobs + (int64_t)P.M * P.plane + p_begin * T;
@@ -38,7 +40,12 @@ __global__ void k_gather(DevPlan P, const double* y, int64_t y_stride, int64_t p
     int64_t p = p_begin + (e >> 6);
     int col = (int)(e & 63);
     int64_t g = P.obs_gidx[p];
-    zp[e] = (col == 0 && g >= 0) ? y[g] : 0.0;
+    double v = 0.0;
+    if (g >= 0) {
+      if (col == 0) v = y[g];
+      else if (col <= px) v = X[(int64_t)(col - 1) * P.n + g];
+    }
+    zp[e] = v;
   }
 }
 
@@ -420,12 +427,12 @@ static double share(double f, int64_t a, int64_t b, int64_t n) { return n > 0 ? 
 
 // data plane of chunk c (z in column 0 of plane M)
 static void gather_chunk(const mra_plan_s& H, const DevPlan& P, int c, const double* y, int64_t y_stride, int nth,
-                         hipStream_t st) {
+                         hipStream_t st, const double* X, int px) {
   const int64_t p0 = H.chunk_row[c], p1 = H.chunk_row[c + 1];
   if (p1 <= p0) return;
   int64_t gx = ((p1 - p0) * T + NT - 1) / NT;
   if (gx > 4096) gx = 4096;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, p0, p1);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, p0, p1, X, px);
 }
 
 // The leaf planes of chunk c: the data plane, the basis rows W^ (eq. priorw
@@ -433,14 +440,14 @@ static void gather_chunk(const mra_plan_s& H, const DevPlan& P, int c, const dou
 // leaf covariances and their factors (forward pass); otherwise the stored
 // factors are used and the work is recomputation (flops not counted).
 hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const double* theta, int nth,
-                              hipStream_t st, int64_t y_stride, bool factor) {
+                              hipStream_t st, int64_t y_stride, bool factor, const double* X, int px) {
   const DevPlan P = chunk_plan(H, c);
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2, nsig = (int64_t)H.sig_tasks.size() / 3;
   const int64_t nfac = (int64_t)H.fac_tasks.size();
-  gather_chunk(H, P, c, y, y_stride, nth, st);
+  gather_chunk(H, P, c, y, y_stride, nth, st, X, px);
   const int64_t r0 = H.ck_row[c], r1 = H.ck_row[c + 1];
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, factor ? "leaf_rows" : "leaf_rows_re", -1,
             factor ? share(F.leaf_rows, r0, r1, nrow) : 0.0, 1, nullptr, k_leaf_rows, r0, r1, theta);
@@ -465,7 +472,7 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
 // launch_forward_back.  With MRA_CHECKPOINT the leaf phase and the leaf
 // products run chunk by chunk here (no side stream).
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                const Side* side, int64_t y_stride) {
+                                const Side* side, int64_t y_stride, const double* X, int px) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
@@ -477,18 +484,19 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
     const int nkl = M * (M + 1) / 2;
     const int64_t nred = (int64_t)H.reduce_order.size();
     for (int c = 0; c < H.nchunks; ++c) {
-      hipError_t e = launch_leaf_planes(H, c, y, theta, nth, st, y_stride, true);
+      hipError_t e = launch_leaf_planes(H, c, y, theta, nth, st, y_stride, true, X, px);
       if (e != hipSuccess) return e;
       const DevPlan Pc = chunk_plan(H, c);
       Runner rc{Pc, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
       rc.tuned(F_LEAF_REDUCE, MAP_GROUPED, "leaf_reduce", -1, share(F.leaf_reduce, H.ck_red[c], H.ck_red[c + 1], nred),
                nkl, nullptr, k_leaf_reduce, H.ck_red[c] * nkl, H.ck_red[c + 1] * nkl);
+      if (X && (e = launch_gls_leaf(H, Pc, H.ck_red[c], H.ck_red[c + 1], px + 1, st)) != hipSuccess) return e;
     }
     return hipGetLastError();
   }
   int64_t gx = (P.npad * T + NT - 1) / NT;
   if (gx > 4096) gx = 4096;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, (int64_t)0, P.npad);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, (int64_t)0, P.npad, X, px);
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,
             (int64_t)H.row_tasks.size() / 2, theta);
   run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, F.sigma, 1, nullptr, k_sigma, 0, (int64_t)H.sig_tasks.size() / 3,

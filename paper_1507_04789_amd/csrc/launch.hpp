@@ -182,8 +182,11 @@ struct Side {
   hipEvent_t fork, big, fork2, join, join2;   // join: V done; join2: L^{-1} done
 };
 // y_stride: parameter row b uses the data y + b * y_stride (0: the same data for all rows)
+// X (may be null): p trend columns [p][n] (caller's order) carried beside the
+// data in columns 1..p of the data plane (generalised least squares)
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
-                                const Side* side = nullptr, int64_t y_stride = 0);
+                                const Side* side = nullptr, int64_t y_stride = 0, const double* X = nullptr,
+                                int px = 0);
 // A callback run once, when the launches of its stage have been enqueued on
 // the main stream: 0 before the leaf reduction, 1 after it, 1 + j after
 // posterior level M - j (and its child sums), j = 1..M, then M + 2 + m after
@@ -217,6 +220,12 @@ hipError_t launch_grad_rest(const mra_plan_s& H, const double* y, int64_t y_stri
 // factor, otherwise recomputed from the stored factors)
 DevPlan chunk_plan(const mra_plan_s& H, int c);
 hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const double* theta, int nth,
-                              hipStream_t st, int64_t y_stride, bool factor);
+                              hipStream_t st, int64_t y_stride, bool factor, const double* X = nullptr,
+                              int px = 0);
+// generalised least squares (gls.hip): the level-(M-1) multi-column leaf
+// products of the reduce-order regions [q0, q1), and the whole call
+hipError_t launch_gls_leaf(const mra_plan_s& H, const DevPlan& P, int64_t q0, int64_t q1, int R, hipStream_t st);
+hipError_t launch_gls(const mra_plan_s& H, const double* y, const double* X, int p, const double* theta, double* beta,
+                      double* out_ll, double* xtsix, double* grad, double* resid, hipStream_t st);
 
 }  // namespace mra

@@ -456,6 +456,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     // gradient partial sums: one slot per task of every gradient-producing launch
     D.n_gpart = P->n_sig_tiles + (int64_t)P->row_tasks.size() / 2 + n_internal + 8;
     D.off_gpart = wtake(D.n_gpart * 4);
+    D.off_gls0 = wtake(3 * TT + 2 * T * T);
   }
   D.off_pw = wtake(std::max(M, 1) * P->ppad * T);
   int64_t nbmax = 1;

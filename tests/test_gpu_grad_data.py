@@ -15,7 +15,7 @@ import pytest
 
 from oracle import predict
 from oracle.geometry import Geometry
-from paper_1507_04789_amd import MRAError, MRALogLik, Plan, MRA_GRAPH, MRA_PLAIN, MRA_SYNC
+from paper_1507_04789_amd import MRAError, MRALogLik, Plan, MRA_CHECKPOINT, MRA_GRAPH, MRA_PLAIN, MRA_SYNC
 from paper_1507_04789_amd import workloads as wl
 
 torch = pytest.importorskip("torch")
@@ -232,13 +232,15 @@ def test_gls_small_against_oracle(M, r, n):
     z = g.standard_normal(n) + X @ np.array([0.5, 1.0, -1.0])
     th = _th(0.9, 0.15, 0.03)
     print("gls case n=%d M=%d r=%d" % (n, M, r), flush=True)
-    p = Plan(locs, M=M, J=4, r=r, cov="matern32")
-    out = p.gls(z, X, th)
     rb, rll, rg, rA = predict.gls(Geometry(locs, 2, M, 4, r), z, X, "matern32", th)
-    np.testing.assert_allclose(out["beta"], rb, rtol=1e-8, atol=1e-10)
-    np.testing.assert_allclose(out["XtSiX"], rA, rtol=1e-9)
-    assert abs(out["loglik"] - rll) <= 1e-10 * abs(rll)
-    assert (np.abs(out["grad"] - rg) <= 1e-6 * np.abs(rg) + 1e-9 * np.abs(rg).max()).all(), (out["grad"], rg)
+    for flags in (MRA_SYNC, MRA_SYNC | MRA_CHECKPOINT):
+        p = Plan(locs, M=M, J=4, r=r, cov="matern32", flags=flags, chunks=3)
+        out = {k: v.cpu().numpy() for k, v in p.gls(z, X, th).items()}
+        np.testing.assert_allclose(out["beta"], rb, rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(out["XtSiX"], rA, rtol=1e-9)
+        assert abs(out["loglik"][0] - rll) <= 1e-10 * abs(rll)
+        assert (np.abs(out["grad"] - rg) <= 1e-6 * np.abs(rg) + 1e-9 * np.abs(rg).max()).all(), (out["grad"], rg)
+        np.testing.assert_allclose(out["resid"], z - X @ rb, rtol=0, atol=1e-9 * np.abs(z).max())
 
 
 def test_gls_full_size_normal_equations():
@@ -253,15 +255,19 @@ def test_gls_full_size_normal_equations():
     p = Plan(w.locs, M=w.M, J=w.J, r=w.r, cov=w.cov, flags=0)
     p.bind("cuda:0")
     th = np.asarray(w.theta)
-    out = p.gls(z, X, th)
+    out = {k: v.cpu().numpy() for k, v in p.gls(z, X, th).items()}
     r = z - X @ out["beta"]
+    np.testing.assert_allclose(out["resid"], r, rtol=0, atol=1e-12 * np.abs(z).max())
+    ll_r, g_r = p.loglik_grad(r, th)      # profile = ordinary loglik at the residual
+    assert abs(float(ll_r[0]) - out["loglik"][0]) <= 1e-10 * abs(out["loglik"][0])
+    assert (np.abs(g_r[0].cpu().numpy() - out["grad"]) <= 1e-6 * np.abs(out["grad"])).all()
     _, _, gy = p.loglik_grad_data(r, th)
     ne = X.T @ gy[0].cpu().numpy()                    # = -X' Sigma^{-1} r
     scale = np.abs(X).T @ np.abs(gy[0].cpu().numpy())
     assert (np.abs(ne) <= 1e-9 * scale).all(), (ne, scale)
     for d in np.eye(3) * 1e-3:
         ll = float(p.loglik(z - X @ (out["beta"] + d), th)[0])
-        assert ll <= out["loglik"]
+        assert ll <= out["loglik"][0]
     del p
     torch.cuda.empty_cache()
 
@@ -285,4 +291,4 @@ def test_data_rows_batch_matches_single_calls():
     z = Y[0] + X @ np.array([0.5, 1.0, -1.0])
     p1 = Plan(locs, M=3, J=4, r=16, cov="matern32", max_theta=1)
     a, b = pb.gls(z, X, ths[0]), p1.gls(z, X, ths[0])
-    assert np.array_equal(a["beta"], b["beta"]) and a["loglik"] == b["loglik"]
+    assert torch.equal(a["beta"], b["beta"]) and torch.equal(a["loglik"], b["loglik"])
