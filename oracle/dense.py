@@ -145,3 +145,27 @@ def exact_krige(locs, z, cov_kind, theta, pred):
     mean = Cps @ np.linalg.solve(V, z)
     var = cov.sigma2 - np.einsum("ij,ji->i", Cps, np.linalg.solve(V, Cps.T))
     return mean, var
+
+
+def mra_krige_joint_dense(geom, z, cov_kind, theta, pred):
+    """Posterior predictive mean and joint covariance of the latent M-RA
+    process at pred: C_M(P, S) Sigma^{-1} z and
+    C_M(P, P) - C_M(P, S) Sigma^{-1} C_M(S, P), all from the chain closed form."""
+    cov = Covariance(cov_kind, theta)
+    V, _ = data_covariance(geom, cov)
+    leafP = geom.leaf_of(pred)
+    Cps, _ = mra_cross(geom, cov, pred, leafP, geom.locs, geom.leaf)
+    Cpp, _ = mra_cross(geom, cov, pred, leafP, pred, leafP)
+    mean = Cps @ np.linalg.solve(V, np.asarray(z, dtype=np.float64))
+    Psi = Cpp - Cps @ np.linalg.solve(V, Cps.T)
+    return mean, 0.5 * (Psi + Psi.T)
+
+
+def exact_krige_joint(locs, z, cov_kind, theta, pred):
+    """Joint simple kriging under the original process."""
+    cov = Covariance(cov_kind, theta)
+    V = cov(locs, locs) + cov.tau2 * np.eye(locs.shape[0])
+    Cps = cov(pred, locs)
+    mean = Cps @ np.linalg.solve(V, z)
+    Psi = cov(pred, pred) - Cps @ np.linalg.solve(V, Cps.T)
+    return mean, Psi

@@ -11,7 +11,8 @@ For prediction locations S^P in leaf R = (M, i) with ancestors a_0..a_M = R:
   mean  = sum_{m<M} B~^{m+1,m} K~_{a_m} w^m_{a_m} + L^M Sigma_R^{-1} z_R
   var   = diag( sum_{m<M} B~^{m+1,m} K~_{a_m} B~^{m+1,m}' + V^P - L^M Sigma_R^{-1} L^M' )
 (eq. prediction: weights eta~_m ~ N(K~ w^m, K~), remainder delta~ with the
-mean and covariance of Prop. 2).  Only the marginal variances are returned.
+mean and covariance of Prop. 2).  predict() returns the marginal variances,
+predict_joint() the joint covariance matrix.
 """
 from __future__ import annotations
 
@@ -84,6 +85,87 @@ def predict(geom: Geometry, z, cov_kind, theta, pred):
         mean[ip] = mu
         var[ip] = vv
     return mean, var
+
+
+def predict_joint(geom: Geometry, z, cov_kind, theta, pred):
+    """(mean, Psi): posterior predictive mean and JOINT covariance of y_M at
+    pred given z, from Prop. 2.  The posterior predictive has the M-RA form
+    sum_{m<M} B~^{m+1,m} eta~_{a_m} + delta~ with independent weights
+    eta~_{a_m} ~ N(K~ w^m, K~) per region and an independent remainder
+    delta~ ~ N(L^M Sigma^{-1} z_R, V^P - L^M Sigma^{-1} L^M') per leaf, so
+      Psi(s, s') = sum over the levels m < M at which s and s' share the
+                   region a_m of  B~^{m+1,m}(s) K~_{a_m} B~^{m+1,m}(s')'
+                 + [s, s' in the same leaf] (V^P - L^M Sigma^{-1} L^M')(s, s'),
+    with V^P the full block C_0(S^P, S^P) - sum_{k<M} U^k K_{a_k} U^k' (the
+    printed upper limit of that sum read as M - 1).  The quantities are those
+    of predict(), kept as full blocks instead of diagonals."""
+    cov = Covariance(cov_kind, theta)
+    _, _, st = loglik(geom, z, cov_kind, theta, grad=False, keep=True)
+    M = geom.M
+    z = np.asarray(z, dtype=np.float64)
+    pred = np.atleast_2d(np.asarray(pred, dtype=np.float64))
+    leafP = geom.leaf_of(pred)
+    npred = pred.shape[0]
+    mean = np.zeros(npred)
+    Psi = np.zeros((npred, npred))
+    leaves = np.unique(leafP)
+    idx = {}
+    fac = {}     # leaf -> [B~^{m+1,m} for m < M]
+    for i in leaves:
+        i = int(i)
+        ip = np.flatnonzero(leafP == i)
+        idx[i] = ip
+        SP = pred[ip]
+        anc = geom.ancestors(M, i)
+        SR = geom.region_points(M, i)
+        zR = z[geom.leaf_obs(i)]
+        WR = st.W[(M, i)]
+        U = []
+        for l in range(M + 1):
+            Ql = SR if l == M else geom.knots[l][anc[l]]
+            u = cov(SP, Ql)
+            for k in range(l):
+                Wk_al = WR[k] if l == M else st.W[(l, anc[l])][k]
+                u = u - U[k] @ cho_solve(st.Kinv[(k, anc[k])].c, Wk_al.v.T)
+            U.append(u)
+        LM = U[M]
+        VP = cov(SP, SP)
+        for k in range(M):
+            VP = VP - U[k] @ cho_solve(st.Kinv[(k, anc[k])].c, U[k].T)
+        Sig = st.Sigma[i]
+        if Sig is not None and Sig.c is not None:
+            Bt = {(M, k): U[k] - LM @ cho_solve(Sig.c, WR[k].v) for k in range(M)}
+            m_leaf = LM @ cho_solve(Sig.c, zR)
+            C_leaf = VP - LM @ cho_solve(Sig.c, LM.T)
+        else:
+            Bt = {(M, k): U[k] for k in range(M)}
+            m_leaf = np.zeros(SP.shape[0])
+            C_leaf = VP
+        for l in range(M - 1, 0, -1):
+            Kt = st.Ktilde[(l, anc[l])] if (l, anc[l]) in st.Ktilde else None
+            for k in range(l):
+                Bt[(l, k)] = (Bt[(l + 1, k)] - Bt[(l + 1, l)] @ cho_solve(Kt.c, st.A[(l, anc[l])][(l, k)].v)
+                              if Kt is not None and Kt.c is not None else Bt[(l + 1, k)])
+        mu = m_leaf.copy()
+        for m in range(M):
+            Kt = st.Ktilde[(m, anc[m])]
+            if Kt.c is None:
+                continue
+            mu += (Bt[(m + 1, m)] @ cho_solve(Kt.c, st.omega[(m, anc[m])][m].v)).ravel()
+        mean[ip] = mu
+        Psi[np.ix_(ip, ip)] += C_leaf
+        fac[i] = [Bt[(m + 1, m)] for m in range(M)]
+    for i in leaves:
+        i = int(i)
+        for j in leaves:
+            j = int(j)
+            ai, aj = geom.ancestors(M, i), geom.ancestors(M, j)
+            for m in range(M):
+                if ai[m] != aj[m]:
+                    break
+                Kt = st.Ktilde[(m, ai[m])]
+                Psi[np.ix_(idx[i], idx[j])] += fac[i][m] @ cho_solve(Kt.c, fac[j][m].T)
+    return mean, Psi
 
 
 def data_gradient(geom: Geometry, z, cov_kind, theta, idx=None):

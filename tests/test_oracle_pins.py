@@ -257,6 +257,32 @@ def test_prediction_matches_dense_kriging(kind, M, r):
     assert (var > 0).all()
 
 
+# P12: the joint posterior predictive covariance of Prop. 2 (independent
+# region weights eta~ and leaf remainders delta~) against the dense closed
+# form C_M(P,P) - C_M(P,S) Sigma^{-1} C_M(S,P) and, at M = 0, textbook joint
+# kriging; its diagonal and the mean against predict()
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("M,r", [(0, 4), (1, 9), (2, 4), (3, 4)])
+def test_joint_prediction_matches_dense(kind, M, r):
+    locs, z = _data(170, seed=30 + M)
+    th = _theta(k=0.25)
+    g = Geometry(locs, 2, M, 4, r)
+    # prediction points sharing leaves, in neighbouring leaves and far apart
+    pred = np.concatenate([np.random.default_rng(98).random((30, 2)), locs[:6] + 1e-3 * (locs[:6] < 0.5)])
+    mu, Psi = predict.predict_joint(g, z, kind, th, pred)
+    if M == 0:
+        mu0, Psi0 = dense.exact_krige_joint(locs, z, kind, th, pred)
+    else:
+        mu0, Psi0 = dense.mra_krige_joint_dense(g, z, kind, th, pred)
+    np.testing.assert_allclose(mu, mu0, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(Psi, Psi0, rtol=1e-9, atol=1e-10)
+    mv, vv = predict.predict(g, z, kind, th, pred)
+    np.testing.assert_allclose(np.diag(Psi), vv, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(mu, mv, rtol=1e-10, atol=1e-12)
+    assert np.allclose(Psi, Psi.T, rtol=0, atol=1e-12)
+    assert np.linalg.eigvalsh(Psi).min() > -1e-10
+
+
 # P11: Sigma(c sigma^2, c tau^2) = c Sigma, so
 # dl/dlog sigma^2 + dl/dlog tau^2 = -(n - u)/2 exactly, at any size
 @pytest.mark.parametrize("kind", COVS)
