@@ -66,6 +66,8 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 #define MRA_GRAPH  4u   /* capture each call's launch sequence in a hipGraph and replay it */
 #define MRA_NO_GRAD 8u  /* mra_loglik and mra_predict only: the work arena leaves out the reverse
                            pass's buffers, and mra_loglik_grad(_data) return MRA_ESTATE */
+#define MRA_JOINT  32u   /* reserve the buffers of mra_predict_cov and mra_simulate (the joint
+                           posterior predictive distribution at the prediction locations) */
 #define MRA_CHECKPOINT 16u /* keep the prior blocks (eq. priorw at levels < M) and the leaf
                            factors, and stream the leaf phase through the tree in chunks of
                            level-(M-1) subtrees: the basis rows W^_R of the leaves (the
@@ -90,7 +92,7 @@ typedef struct {
   double lo[2], hi[2];  /* domain box (only the first d entries are read) */
   int32_t cov;          /* mra_cov */
   int32_t max_theta;    /* largest parameter batch a call may pass (>= 1) */
-  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT */
+  uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT | MRA_JOINT */
   int32_t chunks;       /* MRA_CHECKPOINT: leaf chunks (0: 8; at most the level-(M-1) region count) */
 } mra_config;
 
@@ -104,6 +106,8 @@ typedef struct {
   double flops_loglik;  /* algorithmic FP64 flops of one log-likelihood */
   double flops_grad;    /* algorithmic FP64 flops of one log-likelihood + gradient */
   double flops_predict; /* algorithmic FP64 flops of one prediction pass */
+  int64_t n_sim_normals; /* standard normals per draw of mra_simulate: 64 per region below
+                            level M (sum_{m<M} J^m regions, the first r used) + n_pred */
 } mra_info;
 
 /*
@@ -241,6 +245,36 @@ mra_status mra_loglik_grad_noalloc(mra_plan_t plan, const double* d_y, const dou
  */
 mra_status mra_predict(mra_plan_t plan, const double* d_y, const double* d_theta,
                        double* d_mean, double* d_var, void* stream);
+
+/*
+ * Joint posterior predictive distribution (Prop. 2 and the remark after
+ * it): the posterior predictive of y_M at the prediction locations has the
+ * M-RA form sum_{m<M} B~^{m+1,m} eta~_{a_m} + delta~ with independent region
+ * weights eta~ ~ N(K~ w^m, K~) and leaf remainders delta~ ~ N(L^M Sigma^{-1}
+ * z_R, V^P - L^M Sigma^{-1} L^M'), so its covariance is the sum over shared
+ * regions of B~ K~ B~' plus, within a leaf, the remainder block.  Plans need
+ * MRA_JOINT (otherwise MRA_ESTATE); one parameter vector d_theta[3].
+ *
+ * mra_predict_cov: d_mean[n_pred] and the dense covariance matrix
+ * d_cov[n_pred][n_pred] (row-major, caller's order of h_pred).
+ *
+ * mra_simulate: n_draws (1..MRA_SIM_MAX_DRAWS) conditional draws of y_M at
+ * the prediction locations, d_out[n_draws][n_pred], from caller-supplied
+ * standard normals d_eps[n_draws][eps_stride], eps_stride >= n_sim_normals
+ * of mra_get_info: row d holds 64 normals per region below level M in
+ * level-major, region-major order ((sum_{l<m} J^l + i) * 64 for region
+ * (m, i), of which the first r are used) followed by one normal per
+ * prediction location in the caller's order.  Draw d is
+ *   mean + sum_m B~^{m+1,m} Lt_{a_m}^{-T} xi_{a_m} + chol(remainder block) xi_R
+ * (Lt Lt' the whitened K~^{-1}), a linear function of the normals.  The
+ * prediction locations of a leaf must be distinct (the remainder block is
+ * factored; MRA_ENOTPD otherwise).
+ */
+#define MRA_SIM_MAX_DRAWS 64
+mra_status mra_predict_cov(mra_plan_t plan, const double* d_y, const double* d_theta, double* d_mean,
+                           double* d_cov, void* stream);
+mra_status mra_simulate(mra_plan_t plan, const double* d_y, const double* d_theta, const double* d_eps,
+                        int64_t eps_stride, int32_t n_draws, double* d_out, void* stream);
 
 /* After a call that returned MRA_ENOTPD (or after synchronising a call
  * made without MRA_SYNC): the first failing (theta index, level, region).

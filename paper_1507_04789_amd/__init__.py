@@ -13,9 +13,10 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import MRA_CHECKPOINT, MRA_GRAPH, MRA_NO_GRAD, MRA_PLAIN, MRA_SYNC, MRAError
+from ._lib import MRA_CHECKPOINT, MRA_GRAPH, MRA_JOINT, MRA_NO_GRAD, MRA_PLAIN, MRA_SYNC, MRAError
 
-__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH", "MRA_NO_GRAD", "MRA_CHECKPOINT"]
+__all__ = ["Plan", "MRALogLik", "MRAError", "MRA_SYNC", "MRA_PLAIN", "MRA_GRAPH", "MRA_NO_GRAD", "MRA_CHECKPOINT",
+           "MRA_JOINT"]
 
 _COV = {"exponential": _lib.MRA_COV_EXPONENTIAL, "matern32": _lib.MRA_COV_MATERN32}
 
@@ -281,6 +282,38 @@ class Plan:
                                    self._stream())
         self._fail(s, "mra_predict")
         return mean, var
+
+    def predict_cov(self, y, theta):
+        """(mean [n_pred], cov [n_pred, n_pred]): posterior predictive mean
+        and joint covariance of the latent process at the prediction
+        locations (Prop. 2), for one parameter vector; needs an MRA_JOINT
+        plan."""
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        mean = torch.empty(self.n_pred, dtype=torch.float64, device=self.device)
+        cov = torch.empty(self.n_pred, self.n_pred, dtype=torch.float64, device=self.device)
+        s = _lib.lib().mra_predict_cov(self._h, y.data_ptr(), theta[:1].data_ptr(), mean.data_ptr(), cov.data_ptr(),
+                                       self._stream())
+        self._fail(s, "mra_predict_cov")
+        return mean, cov
+
+    def simulate(self, y, theta, eps):
+        """Conditional draws of the latent process at the prediction
+        locations given y (Prop. 2), one per row of the standard normals
+        eps (n_draws <= 64, each row info["n_sim_normals"] long: 64 per
+        region below level M, then one per prediction location); returns
+        (n_draws, n_pred).  Needs an MRA_JOINT plan."""
+        torch = _torch()
+        y, theta = self._prep(y, theta)
+        eps = torch.as_tensor(eps, dtype=torch.float64).to(self.device)
+        if eps.dim() == 1:
+            eps = eps[None]
+        eps = eps.contiguous()
+        out = torch.empty(eps.shape[0], self.n_pred, dtype=torch.float64, device=self.device)
+        s = _lib.lib().mra_simulate(self._h, y.data_ptr(), theta[:1].data_ptr(), eps.data_ptr(), eps.shape[1],
+                                    eps.shape[0], out.data_ptr(), self._stream())
+        self._fail(s, "mra_simulate")
+        return out
 
     # -- autotuning -------------------------------------------------------------
     def autotune(self, y, theta, reps: int = 3):

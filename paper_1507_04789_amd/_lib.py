@@ -9,13 +9,14 @@ LIB_PATH = os.path.join(HERE, "libmra.so")
 
 MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EHIP, MRA_ESTATE = 0, -1, -2, -3, -4, -5
 MRA_COV_EXPONENTIAL, MRA_COV_MATERN32 = 0, 1
-MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD, MRA_CHECKPOINT = 1, 2, 4, 8, 16
+MRA_SYNC, MRA_PLAIN, MRA_GRAPH, MRA_NO_GRAD, MRA_CHECKPOINT, MRA_JOINT = 1, 2, 4, 8, 16, 32
+SIM_MAX_DRAWS = 64   # MRA_SIM_MAX_DRAWS
 
 # every symbol the header declares
 SYMBOLS = ["mra_build", "mra_requirements", "mra_get_info", "mra_get_geometry", "mra_bind", "mra_loglik",
            "mra_loglik_grad", "mra_loglik_grad_data", "mra_predict", "mra_last_failure", "mra_profile", "mra_profile_read",
            "mra_status_string", "mra_destroy", "mra_autotune", "mra_get_tuning", "mra_set_tuning",
-           "mra_loglik_grad_noalloc", "mra_gls"]
+           "mra_loglik_grad_noalloc", "mra_gls", "mra_predict_cov", "mra_simulate"]
 NOALLOC_MAX_BYTES = 256 << 20   # MRA_NOALLOC_MAX_BYTES
 
 
@@ -28,7 +29,7 @@ class Config(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_pred", C.c_int64), ("n_rows_pad", C.c_int64), ("n_leaves", C.c_int64),
                 ("n_regions", C.c_int64), ("max_leaf", C.c_int64), ("flops_loglik", C.c_double),
-                ("flops_grad", C.c_double), ("flops_predict", C.c_double)]
+                ("flops_grad", C.c_double), ("flops_predict", C.c_double), ("n_sim_normals", C.c_int64)]
 
 
 class PhaseStat(C.Structure):
@@ -64,6 +65,8 @@ def lib() -> C.CDLL:
     L.mra_loglik_grad_data.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, vp]
     L.mra_loglik_grad_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.mra_gls.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.mra_predict_cov.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.mra_simulate.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp]
     L.mra_predict.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mra_last_failure.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp]
     L.mra_profile.argtypes = [vp, i32]

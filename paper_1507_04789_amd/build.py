@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmra.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fwd.hip", "grad.hip", "predict.hip", "gls.hip", "noalloc.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["fwd.hip", "grad.hip", "predict.hip", "gls.hip", "predjoint.hip", "noalloc.hip", "plan.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

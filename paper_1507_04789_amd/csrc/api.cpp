@@ -15,8 +15,11 @@
 namespace mra {
 
 hipError_t launch_predict(const mra_plan_s& H, const double* y, const double* theta, double* mean, double* var,
-                          hipStream_t st);
+                          hipStream_t st, bool keep = false);
 hipError_t noalloc_scratch(void** out);   // noalloc.hip
+hipError_t launch_predict_cov(const mra_plan_s& H, const double* theta, double* cov, hipStream_t st);
+hipError_t launch_simulate(const mra_plan_s& H, const double* theta, const double* eps, int64_t n_eps, int nd,
+                           double* out, hipStream_t st);
 
 namespace {
 
@@ -288,6 +291,7 @@ mra_status mra_get_info(mra_plan_t P, mra_info* info) {
   info->flops_loglik = P->flops_loglik;
   info->flops_grad = P->flops_grad;
   info->flops_predict = P->flops_predict;
+  info->n_sim_normals = P->reg_base[P->M] * T + P->n_pred;
   return MRA_OK;
 }
 
@@ -332,7 +336,11 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
             up(L.g_pgidx, P->pred_gidx.data(), P->pred_gidx.size() * 8) &&
             up(L.g_pt, P->pred_tasks.data(), P->pred_tasks.size() * 4) &&
             up(L.g_pleafn, P->pleaf_n.data(), P->pleaf_n.size() * 4) &&
-            up(L.g_ppoff, P->pleaf_poff.data(), P->pleaf_poff.size() * 8);
+            up(L.g_ppoff, P->pleaf_poff.data(), P->pleaf_poff.size() * 8) &&
+            up(L.g_psoff, P->pleaf_soff.data(), P->pleaf_soff.size() * 8) &&
+            up(L.g_pdoff, P->pleaf_doff.data(), P->pleaf_doff.size() * 8) &&
+            up(L.g_pcdt, P->pcd_tasks.data(), P->pcd_tasks.size() * 4) &&
+            up(L.g_pfact, P->pfac_tasks.data(), P->pfac_tasks.size() * 4);
   if (!ok || hipStreamSynchronize(st) != hipSuccess) return MRA_EHIP;
   DevPlan& D = P->dp;
   D.knot_xy = (const double*)(g + L.g_knot);
@@ -357,6 +365,10 @@ mra_status mra_bind(mra_plan_t P, void* d_geom, size_t geom_bytes, void* d_work,
   D.pred_tasks = (const int32_t*)(g + L.g_pt);
   D.pleaf_n = (const int32_t*)(g + L.g_pleafn);
   D.pleaf_poff = (const int64_t*)(g + L.g_ppoff);
+  D.pleaf_soff = (const int64_t*)(g + L.g_psoff);
+  D.pleaf_doff = (const int64_t*)(g + L.g_pdoff);
+  D.pcd_tasks = (const int32_t*)(g + L.g_pcdt);
+  D.pfac_tasks = (const int32_t*)(g + L.g_pfact);
   D.work = (double*)d_work;
   if (P->graphs) P->graphs->clear();
   P->d_geom = d_geom;
@@ -483,6 +495,48 @@ mra_status mra_predict(mra_plan_t P, const double* d_y, const double* d_theta, d
     if (e != hipSuccess) return e;
     return launch_predict(*P, d_y, d_theta, d_mean, d_var, q);
   }));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
+  return MRA_OK;
+}
+
+mra_status mra_predict_cov(mra_plan_t P, const double* d_y, const double* d_theta, double* d_mean, double* d_cov,
+                           void* stream) {
+  mra_status s = check_call(P, 1);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_theta || !d_mean || !d_cov) return MRA_EINVAL;
+  if (!(P->cfg.flags & MRA_JOINT)) return MRA_ESTATE;
+  if (P->n_pred == 0) return MRA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
+  P->last_nth = 1;
+  // the kriging pass writes its marginal variances into d_cov, which the
+  // covariance tiles then overwrite entirely
+  s = check_hip(launch_forward(*P, d_y, d_theta, 1, nullptr, st));
+  if (s == MRA_OK) s = check_hip(launch_predict(*P, d_y, d_theta, d_mean, d_cov, st, true));
+  if (s == MRA_OK) s = check_hip(launch_predict_cov(*P, d_theta, d_cov, st));
+  if (s != MRA_OK) return s;
+  if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
+  return MRA_OK;
+}
+
+mra_status mra_simulate(mra_plan_t P, const double* d_y, const double* d_theta, const double* d_eps,
+                        int64_t eps_stride, int32_t n_draws, double* d_out, void* stream) {
+  mra_status s = check_call(P, 1);
+  if (s != MRA_OK) return s;
+  if (!d_y || !d_theta || !d_eps || !d_out) return MRA_EINVAL;
+  if (n_draws < 1 || n_draws > SIM_DRAWS) return MRA_EINVAL;
+  if (eps_stride < P->reg_base[P->M] * T + P->n_pred) return MRA_EINVAL;
+  if (!(P->cfg.flags & MRA_JOINT)) return MRA_ESTATE;
+  if (P->n_pred == 0) return MRA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  set_call_work(P);
+  P->last_nth = 1;
+  // the kriging pass writes its mean and variances into d_out, which the
+  // draws then overwrite entirely
+  s = check_hip(launch_forward(*P, d_y, d_theta, 1, nullptr, st));
+  if (s == MRA_OK) s = check_hip(launch_predict(*P, d_y, d_theta, d_out, d_out, st, true));
+  if (s == MRA_OK) s = check_hip(launch_simulate(*P, d_theta, d_eps, eps_stride, n_draws, d_out, st));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
   return MRA_OK;

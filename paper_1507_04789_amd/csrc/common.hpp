@@ -81,6 +81,45 @@ __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const doub
 }
 
 
+// Blocked left-looking Cholesky of a symmetric nb x nb-tile matrix (tiles
+// row-major at base, tile (i, j) at base + (i nb + j) TT, lower tiles read and
+// overwritten by the factor), the inverses of its diagonal tiles at dinv,
+// and the log-determinant over the first nv rows.  Each tile column takes
+// all its updates from the finished columns as one chain of products, then
+// its own step.  ok is cleared if a pivot was not positive.
+__device__ inline double potrf_tiles(double* base, double* dinv, int nb, int nv, double* lds, double* lds_x,
+                                     double* red, bool& ok) {
+  double logdet = 0.0;
+  Acc acc;
+  for (int jb = 0; jb < nb; ++jb) {
+    double* Dj = base + ((int64_t)jb * nb + jb) * TT;
+    const double* Lj = base + (int64_t)jb * nb * TT;   // row jb of tiles
+    acc_load(acc, Dj, T);
+    gemm_segs2(acc, jb, [&](int k) { return seg<Op::N, Op::T>(Lj + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); },
+              lds);
+    acc_to_lds(acc, lds);
+    __syncthreads();
+    ok = potrf_trtri(lds, lds_x, dinv + (int64_t)jb * TT) && ok;
+    logdet += 2.0 * logdiag_lds(lds, min(T, nv - jb * T), red);
+    lds_to_global(lds, Dj);
+    __syncthreads();
+    for (int ib = jb + 1; ib < nb; ++ib) {
+      double* X = base + ((int64_t)ib * nb + jb) * TT;
+      const double* Li = base + (int64_t)ib * nb * TT;
+      acc_load(acc, X, T);
+      gemm_segs2(acc, jb,
+                [&](int k) { return seg<Op::N, Op::T>(Li + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); }, lds);
+      acc_store(acc, X, T);
+      __syncthreads();
+      acc_zero(acc);
+      gemm_segs2(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
+      acc_store(acc, X, T);
+      __syncthreads();
+    }
+  }
+  return logdet;
+}
+
 // reverse-pass storage of region (m, i):
 //   G(l), l <= m   cotangent of A^{m,l} of this region (row m of the posterior cotangent)
 //   wbar_omega()   cotangent of w^m

@@ -9,6 +9,7 @@ namespace mra {
 constexpr int T = 64;                 // tile edge: knots per region are padded to T
 constexpr int64_t TT = (int64_t)T * T;
 constexpr int MAXL = 12;              // levels 0..MAXL-1 supported (M <= 11)
+constexpr int SIM_DRAWS = 64;         // draws of one mra_simulate call (one tile of columns)
 
 // Failure code written to the per-theta status word: 1 + level * 2^40 + region
 __host__ __device__ inline int64_t fail_code(int level, int64_t region) {
@@ -44,6 +45,14 @@ struct DevPlan {
   const int32_t* pred_tasks; // [n_pred_tasks][2] (leaf, first padded prediction row)
   const int32_t* pleaf_n;    // [n_leaves]
   const int64_t* pleaf_poff; // [n_leaves + 1]
+  // joint predictive distribution (MRA_JOINT): per leaf the first tile of its
+  // prediction points' remainder-covariance block (nbp x nbp tiles) and of
+  // its diagonal inverses; tasks (leaf, bi, bj), bi >= bj, of those blocks;
+  // leaves with prediction points
+  const int64_t* pleaf_soff;
+  const int64_t* pleaf_doff;
+  const int32_t* pcd_tasks;
+  const int32_t* pfac_tasks;
 
   // level tables
   int64_t nreg[MAXL];        // J^m
@@ -83,6 +92,11 @@ struct DevPlan {
   // other regions keep their multi-column quantities in their reverse-pass
   // storage, free until the reverse pass) and a scalar area
   int64_t off_gls0;
+  // MRA_JOINT: whitened prior rows U^^k of the prediction points (M planes
+  // [ppad][T]), the remainder blocks and their diagonal inverses, the mean in
+  // leaf order, and the standard normals of up to SIM_DRAWS draws, each row
+  // [n_internal * T region weights | ppad remainder, leaf order]
+  int64_t off_pu, off_pcd, off_pdinv, off_pmean, off_sim, n_sim;
   int64_t pl_stride;
 };
 

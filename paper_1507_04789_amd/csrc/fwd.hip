@@ -124,40 +124,9 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
   double* S = slice(P, th);
   const int64_t poff = P.leaf_poff[leaf];
   const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
-  const int nR = P.leaf_n[leaf];
-  double* base = S + P.off_sig + P.leaf_soff[leaf] * TT;
-  double* dinv = S + P.off_dinv + P.leaf_doff[leaf] * TT;
-  double logdet = 0.0;
   bool ok = true;
-  Acc acc;
-  // left-looking by tile column: each tile takes all its updates from the
-  // finished columns as one chain of products, then its own step
-  for (int jb = 0; jb < nb; ++jb) {
-    double* Dj = base + ((int64_t)jb * nb + jb) * TT;
-    const double* Lj = base + (int64_t)jb * nb * TT;   // row jb of tiles
-    acc_load(acc, Dj, T);
-    gemm_segs2(acc, jb, [&](int k) { return seg<Op::N, Op::T>(Lj + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); },
-              lds);
-    acc_to_lds(acc, lds);
-    __syncthreads();
-    ok = potrf_trtri(lds, lds_x, dinv + (int64_t)jb * TT) && ok;
-    logdet += 2.0 * logdiag_lds(lds, min(T, nR - jb * T), red);
-    lds_to_global(lds, Dj);
-    __syncthreads();
-    for (int ib = jb + 1; ib < nb; ++ib) {
-      double* X = base + ((int64_t)ib * nb + jb) * TT;
-      const double* Li = base + (int64_t)ib * nb * TT;
-      acc_load(acc, X, T);
-      gemm_segs2(acc, jb,
-                [&](int k) { return seg<Op::N, Op::T>(Li + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); }, lds);
-      acc_store(acc, X, T);
-      __syncthreads();
-      acc_zero(acc);
-      gemm_segs2(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
-      acc_store(acc, X, T);
-      __syncthreads();
-    }
-  }
+  const double logdet = potrf_tiles(S + P.off_sig + P.leaf_soff[leaf] * TT, S + P.off_dinv + P.leaf_doff[leaf] * TT, nb,
+                                    P.leaf_n[leaf], lds, lds_x, red, ok);
   if (threadIdx.x == 0) {
     S[P.off_leafd + leaf] = logdet;
     if (!ok) record_failure(P, S, P.M, leaf);

@@ -86,7 +86,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   if (!cfg || (!h_locs && n > 0) || n < 1 || n_pred < 0 || (n_pred > 0 && !h_pred)) return MRA_EINVAL;
   const int d = cfg->d, M = cfg->M, J = cfg->J, r = cfg->r;
   if (d < 1 || d > 2 || M < 0 || M >= MAXL || r < 1 || r > T || cfg->max_theta < 1) return MRA_EINVAL;
-  if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT)) return MRA_EINVAL;
+  if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT | MRA_JOINT)) return MRA_EINVAL;
   if (cfg->chunks < 0) return MRA_EINVAL;
   if (d == 2 && J != 1 && J != 4) return MRA_EINVAL;
   if (d == 1 && (J < 1 || J > 8)) return MRA_EINVAL;
@@ -285,6 +285,29 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     P->cut_rrows[0] = 0;
     P->cut_rrows[8] = (int32_t)nrow;
   }
+  // remainder blocks of each leaf's prediction points (joint distribution)
+  P->pleaf_soff.assign(n_leaves, 0);
+  P->pleaf_doff.assign(n_leaves, 0);
+  P->pcd_tasks.clear();
+  P->pfac_tasks.clear();
+  {
+    int64_t so = 0, dof = 0;
+    for (int64_t i = 0; i < n_leaves; ++i) {
+      const int64_t nbp = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;
+      P->pleaf_soff[i] = so;
+      P->pleaf_doff[i] = dof;
+      so += nbp * nbp;
+      dof += nbp;
+      if (nbp == 0) continue;
+      P->pfac_tasks.push_back((int32_t)i);
+      for (int64_t bi = 0; bi < nbp; ++bi)
+        for (int64_t bj = 0; bj <= bi; ++bj) {
+          P->pcd_tasks.push_back((int32_t)i); P->pcd_tasks.push_back((int32_t)bi); P->pcd_tasks.push_back((int32_t)bj);
+        }
+    }
+    P->n_pcd_tiles = std::max<int64_t>(so, 1);
+    P->n_pdinv_tiles = std::max<int64_t>(dof, 1);
+  }
   P->ck_pred.assign(P->nchunks + 1, 0);
   for (int64_t i = 0; i < n_leaves; ++i) {
     int64_t nb = (P->pleaf_poff[i + 1] - P->pleaf_poff[i]) / T;
@@ -402,6 +425,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.g_pt = take(std::max<size_t>(P->pred_tasks.size(), 1) * 4);
   L.g_pleafn = take(P->pleaf_n.size() * 4);
   L.g_ppoff = take(P->pleaf_poff.size() * 8);
+  L.g_psoff = take(std::max<size_t>(P->pleaf_soff.size(), 1) * 8);
+  L.g_pdoff = take(std::max<size_t>(P->pleaf_doff.size(), 1) * 8);
+  L.g_pcdt = take(std::max<size_t>(P->pcd_tasks.size(), 1) * 4);
+  L.g_pfact = take(std::max<size_t>(P->pfac_tasks.size(), 1) * 4);
   L.geom_bytes = off;
 
   // ---- work arena layout (doubles per theta slice) ----
@@ -464,6 +491,14 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     if (P->pleaf_n[i] > 0) nbmax = std::max<int64_t>(nbmax, (P->leaf_poff[i + 1] - P->leaf_poff[i]) / T);
   D.pl_stride = nbmax * TT;
   D.off_pl = wtake(std::max<int64_t>((int64_t)P->pred_tasks.size() / 2, 1) * D.pl_stride);
+  if ((cfg->flags & MRA_JOINT) && n_pred > 0) {
+    D.off_pu = wtake(std::max(M, 1) * P->ppad * T);
+    D.off_pcd = wtake(P->n_pcd_tiles * TT);
+    D.off_pdinv = wtake(P->n_pdinv_tiles * TT);
+    D.off_pmean = wtake(P->ppad);
+    D.n_sim = n_internal * T + P->ppad;
+    D.off_sim = wtake((int64_t)SIM_DRAWS * D.n_sim);
+  }
   D.theta_stride = w;
   L.theta_stride = w;
 

@@ -29,6 +29,7 @@ struct Layout {
   size_t g_knot, g_obs, g_gidx, g_leafn, g_poff, g_soff, g_doff, g_rowt, g_sigt, g_fact, g_trst, g_lint, g_rord;
   size_t g_slotp, g_slotq, g_actp, g_actq;
   size_t g_pxy, g_pgidx, g_pt, g_pleafn, g_ppoff, geom_bytes;
+  size_t g_psoff, g_pdoff, g_pcdt, g_pfact;
   // work arena (doubles per theta slice)
   int64_t theta_stride;
 };
@@ -53,6 +54,9 @@ struct mra_plan_s {
   std::vector<int64_t> pperm, pleaf_off;
   std::vector<int32_t> pleaf_n;
   std::vector<int64_t> pleaf_poff;
+  std::vector<int64_t> pleaf_soff, pleaf_doff;   // remainder-block tiles of each leaf's prediction points
+  std::vector<int32_t> pcd_tasks, pfac_tasks;
+  int64_t n_pcd_tiles = 0, n_pdinv_tiles = 0;
   int64_t ppad = 0;
   std::vector<double> pred_xy;
   std::vector<int64_t> pred_gidx;

@@ -26,8 +26,9 @@ __device__ __forceinline__ double row_dot(const double* a, const double* b) {
   return s;
 }
 
-// one 64-row prediction tile
-__global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, double* mean, double* var,
+// one 64-row prediction tile; with keep (MRA_JOINT) the whitened prior rows
+// U^^k are also kept (off_pu) and the mean written in leaf order (off_pmean)
+__global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, double* mean, double* var, int keep,
                                                 TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
@@ -45,6 +46,10 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
   double* U = S + P.off_pw + q0 * T;      // plane l at U + l * ppad * T
   const int64_t pplane = P.ppad * T;
   row_sweep(P, S, c, X, nx, U, pplane, M, leaf, lds, lds + LDS_DOUBLES);
+  if (keep) {
+    for (int k = 0; k < M; ++k)
+      for (int e = threadIdx.x; e < TT; e += NT) S[P.off_pu + (int64_t)k * pplane + q0 * T + e] = U[(int64_t)k * pplane + e];
+  }
   // leaf quantities
   const int64_t poff = P.leaf_poff[leaf];
   const int nb = (int)((P.leaf_poff[leaf + 1] - poff) / T);
@@ -138,13 +143,15 @@ __global__ __launch_bounds__(NT) void k_predict(DevPlan P, const double* theta, 
       mean[g] = mu[threadIdx.x];
       var[g] = vv[threadIdx.x];
     }
+    if (keep) S[P.off_pmean + q0 + threadIdx.x] = g >= 0 ? mu[threadIdx.x] : 0.0;
   }
 }
 
 // after the forward pass; with MRA_CHECKPOINT the leaf planes W^ and Y of
 // each chunk are recomputed (from y) before its prediction tiles
 hipError_t launch_predict(const mra_plan_s& H, const double* y, const double* theta, double* mean, double* var,
-                          hipStream_t st) {
+                          hipStream_t st, bool keep) {
+  const int kp = keep ? 1 : 0;
   const int64_t npt = (int64_t)H.pred_tasks.size() / 2;
   if (H.nchunks > 1) {
     for (int c = 0; c < H.nchunks; ++c) {
@@ -155,13 +162,13 @@ hipError_t launch_predict(const mra_plan_s& H, const double* y, const double* th
       const DevPlan P = chunk_plan(H, c);
       Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
       run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, npt ? H.pf.predict * (double)(t1 - t0) / (double)npt : 0.0,
-                1, nullptr, k_predict, t0, t1, theta, mean, var);
+                1, nullptr, k_predict, t0, t1, theta, mean, var, kp);
     }
     return hipGetLastError();
   }
   const DevPlan& P = H.dp;
   Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
-  run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, H.pf.predict, 1, nullptr, k_predict, 0, npt, theta, mean, var);
+  run.tuned(F_PREDICT, MAP_CHUNKED, "predict", -1, H.pf.predict, 1, nullptr, k_predict, 0, npt, theta, mean, var, kp);
   return hipGetLastError();
 }
 
