@@ -33,7 +33,7 @@ def mra_cross(geom: Geometry, cov: Covariance, X, leafX, Y, leafY, grad=False):
     """C_M(X, Y) (and its (3, ...) tangents) by the chain closed form.
 
     leafX, leafY: leaf indices of the points.  Returns (value, tangents)."""
-    M, J = geom.M, geom.J
+    M = geom.M
     X = np.atleast_2d(X)
     Y = np.atleast_2d(Y)
     out = np.zeros((X.shape[0], Y.shape[0]))
@@ -41,10 +41,10 @@ def mra_cross(geom: Geometry, cov: Covariance, X, leafX, Y, leafY, grad=False):
     # deepest common level of every pair
     mstar = np.full(out.shape, M, dtype=np.int64)
     for m in range(M - 1, -1, -1):
-        ax = leafX // (J ** (M - m))
-        ay = leafY // (J ** (M - m))
-        ax1 = leafX // (J ** (M - m - 1))
-        ay1 = leafY // (J ** (M - m - 1))
+        ax = geom.ancestor_index(leafX, m)
+        ay = geom.ancestor_index(leafY, m)
+        ax1 = geom.ancestor_index(leafX, m + 1)
+        ay1 = geom.ancestor_index(leafY, m + 1)
         sel = (ax[:, None] == ay[None, :]) & (ax1[:, None] != ay1[None, :])
         mstar[sel] = m
     same = mstar == M
@@ -54,9 +54,10 @@ def mra_cross(geom: Geometry, cov: Covariance, X, leafX, Y, leafY, grad=False):
         if grad:
             tout[:, same] = t[:, same]
     for m in range(M):
-        for i in range(J ** m):
-            ix = np.flatnonzero(leafX // (J ** (M - m)) == i)
-            iy = np.flatnonzero(leafY // (J ** (M - m)) == i)
+        axm, aym = geom.ancestor_index(leafX, m), geom.ancestor_index(leafY, m)
+        for i in range(geom.nreg[m]):
+            ix = np.flatnonzero(axm == i)
+            iy = np.flatnonzero(aym == i)
             if ix.size == 0 or iy.size == 0:
                 continue
             blk = mstar[np.ix_(ix, iy)] == m

@@ -169,11 +169,12 @@ def leaf_quantities(geom, cov, Ws, zR, grad):
     return Sig, At, om, Sig.logdet(), Dual(u.v[0, 0], None if u.t is None else u.t[:, 0, 0])
 
 
-def _zero_like_blocks(M, r, grad):
+def _zero_like_blocks(M, rl, grad):
+    """Leaf quantities of an empty leaf: A~^{k,l} (r_k x r_l), w~^k (r_k), d, u."""
     def z(shape):
         return Dual(np.zeros(shape), np.zeros((P,) + shape) if grad else None)
-    At = {(k, l): z((r, r)) for k in range(M) for l in range(k + 1)}
-    om = [z((r, 1)) for _ in range(M)]
+    At = {(k, l): z((rl[k], rl[l])) for k in range(M) for l in range(k + 1)}
+    om = [z((rl[k], 1)) for k in range(M)]
     return At, om, z(()), z(())
 
 
@@ -192,23 +193,23 @@ def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bo
         raise ValueError("child_order must be 'forward' or 'reversed'")
     order = (lambda n: range(n)) if child_order == "forward" else (lambda n: range(n - 1, -1, -1))
     cov = Covariance(cov_kind, theta)
-    M, J, r = geom.M, geom.J, geom.r
+    M, nreg = geom.M, geom.nreg
     z = np.asarray(z, dtype=np.float64)
     st = MRAState()
     # prior quantities of the internal levels, top-down (eq. priorw)
     for m in range(M):
-        for i in range(J ** m):
+        for i in range(nreg[m]):
             Ws = prior_region(geom, cov, st, m, i, grad)
             st.W[(m, i)] = Ws
             st.Kinv[(m, i)] = SPD(Ws[m])
     # leaves and the first posterior level: each level-(M-1) region sums its
     # children's leaf quantities (eq. mainquantities)
     child_sum = {}
-    for i in order(J ** M):
+    for i in order(nreg[M]):
         Ws = prior_region(geom, cov, st, M, i, grad)
         zR = z[geom.leaf_obs(i)]
         if zR.shape[0] == 0:
-            At, om, dR, uR = _zero_like_blocks(M, r, grad)
+            At, om, dR, uR = _zero_like_blocks(M, geom.rl, grad)
             Sig = None
         else:
             Sig, At, om, dR, uR = leaf_quantities(geom, cov, Ws, zR, grad)
@@ -216,14 +217,14 @@ def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bo
             st.W[(M, i)] = Ws
             st.Sigma[i] = Sig
         st.d[(M, i)], st.u[(M, i)] = dR, uR
-        _accumulate(child_sum, (M - 1, i // J) if M > 0 else None, At, om, dR, uR)
+        _accumulate(child_sum, (M - 1, geom.parent(M, i)) if M > 0 else None, At, om, dR, uR)
     if M == 0:
         ll = -0.5 * (st.d[(0, 0)] + st.u[(0, 0)]).v - 0.5 * geom.locs.shape[0] * math.log(2 * math.pi)
         g = None if not grad else -0.5 * (st.d[(0, 0)].t + st.u[(0, 0)].t)
         return ll, g, st
     # posterior recursion, bottom-up (eq. posterior, helpquantities, Sec. 3.3)
     for m in range(M - 1, -1, -1):
-        for i in order(J ** m):
+        for i in order(nreg[m]):
             A, om, dsum, usum = child_sum.pop((m, i))
             Kinv = st.Kinv[(m, i)]
             Kt = SPD(Kinv.A + A[(m, m)])
@@ -243,7 +244,7 @@ def loglik(geom: Geometry, z, cov_kind: str, theta, grad: bool = False, keep: bo
                 for l in range(k + 1):
                     At[(k, l)] = A[(k, l)] - Am[k].T @ KtAm[l]
             omt = [om[k] - Am[k].T @ Ktw for k in range(m)]
-            _accumulate(child_sum, (m - 1, i // J), At, omt, dR, uR)
+            _accumulate(child_sum, (m - 1, geom.parent(m, i)), At, omt, dR, uR)
     root_d, root_u = st.d[(0, 0)], st.u[(0, 0)]
     n = geom.locs.shape[0]
     ll = -0.5 * (root_d.v + root_u.v) - 0.5 * n * math.log(2 * math.pi)

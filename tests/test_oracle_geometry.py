@@ -29,7 +29,7 @@ def test_leaf_boxes_and_children(d, J, M, r):
     for p in range(locs.shape[0]):
         i = int(g.leaf[p])
         for m in range(M, -1, -1):
-            assert _inside(locs[p], g.bounds[m][i // (J ** (M - m))])
+            assert _inside(locs[p], g.bounds[m][g.ancestor_index([i], m)[0]])
     # children tile their parent (volume and containment)
     for m in range(M):
         for i in range(J ** m):
@@ -83,3 +83,34 @@ def test_swath_workload_shape():
     # every point is within half a strip width of some line x - y = c
     dist = np.abs((pts[:, 0] - pts[:, 1])[:, None] - geom.centers[None, :]) / np.sqrt(2)
     assert (dist.min(axis=1) <= geom.width / 2 + 1e-12).all()
+
+
+@pytest.mark.parametrize("Jl,adaptive", [((2, 2, 4, 8), False), ((2, 8, 16), False), ((2, 2, 4, 8), True),
+                                         ((4, 4, 4), True), ((8, 2), True)])
+def test_mixed_and_adaptive_partitions(Jl, adaptive):
+    """Level-dependent J_m and data-adaptive splits: every point lies in the
+    boxes of its leaf and ancestors, the children of a region tile it (area
+    and containment), split values of adaptive splits are quantiles of the
+    region's points, and the leaf assignment of prediction points agrees
+    with that of the observations."""
+    w = wl.clustered(n=6000, M=len(Jl))
+    M = len(Jl)
+    g = Geometry(w.locs, 2, M, 4, 4, J_levels=Jl, r_levels=[4] * M, adaptive=adaptive)
+    for p in range(0, 6000, 7):
+        i = int(g.leaf[p])
+        for m in range(M, -1, -1):
+            assert _inside(w.locs[p], g.bounds[m][g.ancestor_index([i], m)[0]])
+    for m in range(M):
+        J = Jl[m]
+        for i in range(g.nreg[m]):
+            par = g.bounds[m][i]
+            ch = g.bounds[m + 1][i * J:(i + 1) * J]
+            cv = np.prod(ch[:, :, 1] - ch[:, :, 0], axis=1)
+            assert abs(cv.sum() - np.prod(par[:, 1] - par[:, 0])) <= 1e-12
+            for c in ch:
+                assert (c[:, 0] >= par[:, 0]).all() and (c[:, 1] <= par[:, 1]).all()
+    assert (g.leaf_of(w.locs) == g.leaf).all()
+    if adaptive:
+        # each split divides its region's points into (nearly) equal parts
+        m0 = np.bincount(g.ancestor_index(g.leaf, 1), minlength=Jl[0])
+        assert m0.max() - m0.min() <= Jl[0]

@@ -124,6 +124,61 @@ def test_1d_exponential_boundary_knots_exact(J, M):
     np.testing.assert_allclose(var, var0, rtol=1e-8, atol=1e-9)
 
 
+# P4 with level-dependent J_m and r_m: the knots of a region are the split
+# points of its next-level partition, r_m = J_{m+1} - 1 (screening of the
+# 1-D exponential makes the M-RA exact for any J_m)
+@pytest.mark.parametrize("Jl", [(2, 3, 2, 4), (4, 2, 3), (3, 1, 2)])
+def test_1d_exponential_boundary_knots_exact_mixed_levels(Jl):
+    g0 = np.random.default_rng(13)
+    n = 120
+    locs = g0.random((n, 1))
+    z = g0.standard_normal(n)
+    th = _theta(k=0.3, t2=0.05)
+    M = len(Jl)
+    rl = [max(Jl[m] - 1, 1) for m in range(M)]
+    nreg = [1]
+    for J in Jl:
+        nreg.append(nreg[-1] * J)
+    g0k = Geometry(locs, 1, M, 2, 1, J_levels=Jl, r_levels=rl, knots=[
+        np.full((nreg[m], rl[m], 1), 0.5) for m in range(M)])   # boxes only
+    knots = []
+    for m in range(M):
+        kk = np.empty((nreg[m], rl[m], 1))
+        for i in range(nreg[m]):
+            a, b = g0k.bounds[m][i][0]
+            J = Jl[m]
+            if J == 1:        # no split below: any interior knot keeps the chain exact
+                kk[i, 0, 0] = a + 0.3 * (b - a)
+            for k in range(1, J):
+                kk[i, k - 1, 0] = a + ((b - a) * k) / J
+        knots.append(kk)
+    g = Geometry(locs, 1, M, 2, 1, J_levels=Jl, r_levels=rl, knots=knots)
+    assert g.nreg == nreg
+    ll, gr, _ = mra.loglik(g, z, "exponential", th, grad=True)
+    ref = _exact_scipy(locs, z, "exponential", th)
+    assert abs(ll - ref) <= 1e-10 * abs(ref)
+    fd = _fd(lambda t: _exact_scipy(locs, z, "exponential", t), th)
+    np.testing.assert_allclose(gr, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+    pred = g0.random((25, 1))
+    mu, var = predict.predict(g, z, "exponential", th, pred)
+    mu0, var0 = dense.exact_krige(locs, z, "exponential", th, pred)
+    np.testing.assert_allclose(mu, mu0, rtol=1e-8, atol=1e-9)
+    np.testing.assert_allclose(var, var0, rtol=1e-8, atol=1e-9)
+
+
+# P2 with level-dependent r_m: one child per level keeps every knot set in
+# one chain, so the M-RA is exact for any M and r_m
+def test_single_child_mixed_r_exact():
+    locs, z = _data(120, seed=14)
+    th = _theta()
+    rl = [4, 9, 2]
+    kn = [np.random.default_rng(15 + m).random((1, rl[m], 2)) for m in range(3)]
+    g = Geometry(locs, 2, 3, 1, 1, J_levels=[1, 1, 1], r_levels=rl, knots=kn)
+    ll, gr, _ = mra.loglik(g, z, "matern32", th, grad=True)
+    ref = _exact_scipy(locs, z, "matern32", th)
+    assert abs(ll - ref) <= 1e-10 * abs(ref)
+
+
 def test_1d_default_knots_midpoint_exact():
     """J = 2, r = 1: the default cell-centred knot is the split point."""
     g0 = np.random.default_rng(4)
@@ -133,6 +188,27 @@ def test_1d_default_knots_midpoint_exact():
     g = Geometry(locs, 1, 4, 2, 1)
     ll, _, _ = mra.loglik(g, z, "exponential", th)
     assert abs(ll - _exact_scipy(locs, z, "exponential", th)) <= 1e-10 * abs(ll)
+
+
+# P5 with level-dependent J_m, r_m (2-D splits into 2, 4 and 8 children)
+# and data-adaptive splits: recursion versus the brute-force dense covariance
+@pytest.mark.parametrize("kind", COVS)
+@pytest.mark.parametrize("Jl,rl,adaptive", [((2, 4, 8), (9, 4, 4), False), ((2, 2, 4), (16, 9, 4), True),
+                                            ((4, 8), (4, 9), True), ((16,), (9,), False)])
+def test_mixed_levels_match_bruteforce(kind, Jl, rl, adaptive):
+    locs, z = _data(190, seed=40 + len(Jl))
+    locs[:60] = 0.3 + 0.05 * locs[:60]      # a cluster, so adaptive splits differ from equal-area ones
+    th = _theta(s2=0.8, k=0.15, t2=0.02)
+    g = Geometry(locs, 2, len(Jl), 4, 4, J_levels=Jl, r_levels=rl, adaptive=adaptive)
+    ll, gr, st = mra.loglik(g, z, kind, th, grad=True)
+    lld, grd = dense.mra_loglik_dense(g, z, kind, th, grad=True)
+    assert abs(ll - lld) <= 1e-11 * abs(lld)
+    np.testing.assert_allclose(gr, grd, rtol=1e-9, atol=1e-9 * np.abs(grd).max())
+    pred = np.random.default_rng(41).random((30, 2))
+    mu, Psi = predict.predict_joint(g, z, kind, th, pred)
+    mu0, Psi0 = dense.mra_krige_joint_dense(g, z, kind, th, pred)
+    np.testing.assert_allclose(mu, mu0, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(Psi, Psi0, rtol=1e-9, atol=1e-10)
 
 
 # P5 / P9 / P12: recursion versus the brute-force dense M-RA covariance
