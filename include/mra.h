@@ -94,6 +94,20 @@ typedef struct {
   int32_t max_theta;    /* largest parameter batch a call may pass (>= 1) */
   uint32_t flags;       /* MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT | MRA_JOINT */
   int32_t chunks;       /* MRA_CHECKPOINT: leaf chunks (0: 8; at most the level-(M-1) region count) */
+  /* Level-dependent partition (Sec. 2.2 with one J per level, as in the
+   * satellite application of Sec. 4.2): J_level[m-1] children per region of
+   * level m-1 (m = 1..M; 0 = J), r_level[m] knots per region of level m
+   * (m = 0..M-1; 0 = r).  d = 2 takes 1, 2, 4, 8 or 16 children per split, a
+   * g_x x g_y grid (1x1, 2x1, 2x2, 4x2, 4x4, the larger count along the
+   * longer side, x on ties), cut first along y then each slab along x; child
+   * iy * g_x + ix.  adaptive = 1 places the split values at quantiles of the
+   * observations in the region (then in each slab): t_k = (v[i-1] + v[i]) / 2,
+   * v sorted, i = (k * len(v)) / g; fewer than g points fall back to equal
+   * parts.  Equal-area split values: a + ((b - a) k) / g, 2-D two-way splits
+   * at (a + b) / 2.  Points on a split value go to the upper child. */
+  int32_t J_level[12];
+  int32_t r_level[12];
+  int32_t adaptive;
 } mra_config;
 
 typedef struct {
@@ -114,10 +128,11 @@ typedef struct {
  * Build a plan: partition the box, assign observations and prediction
  * locations to leaves, place knots (Sec. 2.2, 2.5).  Host only; touches no
  * GPU.  h_locs: n x d row-major; h_pred: n_pred x d (may be NULL with
- * n_pred = 0); h_knots: optional explicit knots, (sum_{m<M} J^m) x r x d in
- * level-major, region-major order, NULL for the default cell-centred grid.
- * Splits: d = 2, J = 4 at the midpoint 0.5*(a+b) of each side, child
- * 2*[y >= ymid] + [x >= xmid]; d = 1 at a + ((b-a)*j)/J.  Returns
+ * n_pred = 0); h_knots: optional explicit knots, r_m x d per region of
+ * level m < M in level-major, region-major order, NULL for the default
+ * cell-centred grid.  Splits as described at mra_config; d = 2, J = 4: at the midpoint
+ * 0.5*(a+b) of each side, child 2*[y >= ymid] + [x >= xmid]; d = 1 at
+ * a + ((b-a)*j)/J.  Returns
  * MRA_EINVAL for out-of-box or non-finite locations or unsupported
  * settings, MRA_ENOMEM if a host allocation fails.  *out is owned by the
  * caller and released with mra_destroy.
@@ -136,7 +151,8 @@ mra_status mra_get_info(mra_plan_t plan, mra_info* info);
 /* Geometry as built, for checking against an independent implementation.
  * Any pointer may be NULL.  h_perm[n]: original index of the k-th
  * observation in leaf order; h_leaf_offsets[J^M + 1]: CSR offsets of the
- * leaves in that order; h_knots: (sum_{m<M} J^m) x r x d.  Host only. */
+ * leaves in that order (J_1 ... J_M leaves); h_knots: r_m x d per region of
+ * level m < M, level-major.  Host only. */
 mra_status mra_get_geometry(mra_plan_t plan, int64_t* h_perm, int64_t* h_leaf_offsets,
                             double* h_knots);
 

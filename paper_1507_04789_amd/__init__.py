@@ -31,14 +31,18 @@ class Plan:
 
     locs: (n, d) float64 observation locations; pred: optional (n_pred, d)
     prediction locations; knots: optional explicit knots, a list over levels
-    m < M of arrays (J^m, r, d); chunks: leaf chunks of an MRA_CHECKPOINT
-    plan (0: the library's default).  The geometry is built on the host; device
+    m < M of arrays (regions of level m, r_m, d); chunks: leaf chunks of an
+    MRA_CHECKPOINT plan (0: the library's default); J_levels (J_1..J_M) and
+    r_levels (r_0..r_{M-1}): children and knots per level instead of J and
+    r; adaptive: split values at quantiles of the observations (see
+    mra_config in include/mra.h).  The geometry is built on the host; device
     arenas are allocated with torch and bound on first use (or bind()).
     """
 
     def __init__(self, locs, *, M: int, J: int, r: int, cov: str, d: int | None = None,
                  lo=None, hi=None, pred=None, knots=None, max_theta: int = 1,
-                 flags: int = MRA_SYNC, chunks: int = 0):
+                 flags: int = MRA_SYNC, chunks: int = 0, J_levels=None, r_levels=None,
+                 adaptive: bool = False):
         L = _lib.lib()
         locs = np.ascontiguousarray(np.asarray(locs, dtype=np.float64))
         if locs.ndim == 1:
@@ -56,6 +60,17 @@ class Plan:
         cfg.max_theta = max_theta
         cfg.flags = flags
         cfg.chunks = chunks
+        self.Jl = [1] + [int(x) for x in (J_levels if J_levels is not None else [J] * M)]
+        self.rl = [int(x) for x in (r_levels if r_levels is not None else [r] * M)]
+        if len(self.Jl) != M + 1 or len(self.rl) != M or M > 12:
+            raise ValueError("J_levels and r_levels need M entries (M <= 11)")
+        for m in range(M):
+            cfg.J_level[m] = self.Jl[m + 1]
+            cfg.r_level[m] = self.rl[m]
+        cfg.adaptive = 1 if adaptive else 0
+        self.nreg = [1]
+        for m in range(1, M + 1):
+            self.nreg.append(self.nreg[-1] * self.Jl[m])
         self.cfg = cfg
         self.cov = cov
         self.max_theta = max_theta
@@ -83,14 +98,19 @@ class Plan:
 
     # -- host-side queries --------------------------------------------------
     def geometry(self):
-        """(perm, leaf_offsets, knots) as built by the library."""
+        """(perm, leaf_offsets, knots) as built by the library; knots is a
+        list over levels m < M of arrays (regions of level m, r_m, d)."""
         L = _lib.lib()
         perm = np.empty(self.n, dtype=np.int64)
-        off = np.empty(self.J ** self.M + 1, dtype=np.int64)
-        nint = sum(self.J ** m for m in range(self.M))
-        kn = np.empty(max(nint * self.r * self.d, 1), dtype=np.float64)
+        off = np.empty(self.nreg[self.M] + 1, dtype=np.int64)
+        sizes = [self.nreg[m] * self.rl[m] * self.d for m in range(self.M)]
+        kn = np.empty(max(sum(sizes), 1), dtype=np.float64)
         _lib.check(L.mra_get_geometry(self._h, perm.ctypes.data, off.ctypes.data, kn.ctypes.data), "mra_get_geometry")
-        return perm, off, kn[:nint * self.r * self.d].reshape(nint, self.r, self.d)
+        out, q = [], 0
+        for m in range(self.M):
+            out.append(kn[q:q + sizes[m]].reshape(self.nreg[m], self.rl[m], self.d))
+            q += sizes[m]
+        return perm, off, out
 
     # -- device ---------------------------------------------------------------
     def bind(self, device="cuda", work: bool = True):

@@ -23,7 +23,8 @@ NOALLOC_MAX_BYTES = 256 << 20   # MRA_NOALLOC_MAX_BYTES
 class Config(C.Structure):
     _fields_ = [("d", C.c_int32), ("M", C.c_int32), ("J", C.c_int32), ("r", C.c_int32),
                 ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("cov", C.c_int32),
-                ("max_theta", C.c_int32), ("flags", C.c_uint32), ("chunks", C.c_int32)]
+                ("max_theta", C.c_int32), ("flags", C.c_uint32), ("chunks", C.c_int32),
+                ("J_level", C.c_int32 * 12), ("r_level", C.c_int32 * 12), ("adaptive", C.c_int32)]
 
 
 class Info(C.Structure):

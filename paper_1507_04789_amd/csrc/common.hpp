@@ -19,7 +19,7 @@ __device__ __forceinline__ const double* knots_of(const DevPlan& P, int m, int64
   return P.knot_xy + (P.reg_base[m] + i) * (2 * T);
 }
 __device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, int l) {
-  for (int q = m; q > l; --q) i /= P.J;
+  for (int q = m; q > l; --q) i /= P.Jl[q];
   return i;
 }
 __device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
@@ -66,7 +66,7 @@ __device__ void row_sweep(const DevPlan& P, double* S, const CovP& c, const doub
   for (int l = 0; l < lev; ++l) {
     const int64_t al = ancestor(P, lev, idx, l);
     const double* Pa = prior_reg(P, S, l, al);
-    acc_cov(acc, X, nx, knots_of(P, l, al), P.r, c, false, 0.0);
+    acc_cov(acc, X, nx, knots_of(P, l, al), P.rl[l], c, false, 0.0);
     gemm_segs2(acc, l, [&](int k) { return seg<Op::N, Op::T>(rows + k * bstride, T, Pa + k * TT, T, -1.0); }, lds,
               mrows);
     double* out = rows + l * bstride;

@@ -17,7 +17,9 @@ __host__ __device__ inline int64_t fail_code(int level, int64_t region) {
 }
 
 struct DevPlan {
-  int32_t d, M, J, r, cov;
+  int32_t d, M, cov;
+  int32_t Jl[MAXL];          // Jl[m]: children per region of level m - 1 (m = 1..M)
+  int32_t rl[MAXL];          // rl[m]: knots per region of level m (m = 0..M-1)
   int64_t n, npad, n_leaves, ppad, n_pred;
 
   // geometry arena

@@ -61,11 +61,12 @@ __global__ __launch_bounds__(NT, 2) void k_prior(DevPlan P, const double* theta,
   const CovP c = load_cov(theta + 3 * th, P.cov);
   double* reg = prior_reg(P, S, m, i);
   const double* X = knots_of(P, m, i);
-  row_sweep(P, S, c, X, P.r, reg, TT, m, i, lds, lds_x);   // lds_x is free until the factorisation
+  const int rm = P.rl[m];
+  row_sweep(P, S, c, X, rm, reg, TT, m, i, lds, lds_x);   // lds_x is free until the factorisation
   Acc acc;
-  acc_cov(acc, X, P.r, X, P.r, c, true, 0.0);
+  acc_cov(acc, X, rm, X, rm, c, true, 0.0);
   gemm_segs2(acc, m, [&](int k) { return seg<Op::N, Op::T>(reg + k * TT, T, reg + k * TT, T, -1.0); }, lds,
-            round16(P.r));
+            round16(rm));
   acc_to_lds(acc, lds);
   __syncthreads();
   if (!potrf_trtri(lds, lds_x, reg + (m + 1) * TT) && threadIdx.x == 0) record_failure(P, S, m, i);
@@ -193,14 +194,15 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
   const double* Yz = S + P.off_y + (int64_t)M * P.plane;
   Acc acc;
   acc_zero(acc);
-  // segments: the row blocks of the J children, K = valid rows rounded to 16
+  // segments: the row blocks of the J_M children, K = valid rows rounded to 16
+  const int JM = P.Jl[M];
   int nsg = 0;
-  for (int c = 0; c < P.J; ++c) {
-    const int64_t leaf = pidx * P.J + c;
+  for (int c = 0; c < JM; ++c) {
+    const int64_t leaf = pidx * JM + c;
     nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
   gemm_segs2(acc, nsg, [&](int sg) {
-    int64_t leaf = pidx * P.J;
+    int64_t leaf = pidx * JM;
     int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
     while (sg >= nbl) {
       sg -= nbl;
@@ -215,8 +217,8 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
   if (k == l) {      // w^k = sum_c Y^k_c' y_c: column threadIdx & 63, rows split over the waves
     const int col = threadIdx.x & 63;
     double w[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c < P.J; ++c) {
-      const int64_t leaf = pidx * P.J + c;
+    for (int c = 0; c < JM; ++c) {
+      const int64_t leaf = pidx * JM + c;
       const int64_t end = P.leaf_poff[leaf] + P.leaf_n[leaf];
       int64_t p = P.leaf_poff[leaf] + wave_id();
       for (; p + 12 < end; p += 16) {   // four rows in flight
@@ -230,15 +232,15 @@ __global__ __launch_bounds__(NT) void k_leaf_reduce(DevPlan P, TaskMap tm) {
   }
   if (kl == 0) {
     double u = 0.0;
-    for (int c = 0; c < P.J; ++c) {
-      const int64_t leaf = pidx * P.J + c;
+    for (int c = 0; c < JM; ++c) {
+      const int64_t leaf = pidx * JM + c;
       for (int64_t p = P.leaf_poff[leaf] + threadIdx.x; p < P.leaf_poff[leaf] + P.leaf_n[leaf]; p += NT)
         u += Yz[p * T] * Yz[p * T];
     }
     u = block_sum(u, red);
     if (threadIdx.x == 0) {
       double dsum = 0.0;
-      for (int c = 0; c < P.J; ++c) dsum += S[P.off_leafd + pidx * P.J + c];
+      for (int c = 0; c < JM; ++c) dsum += S[P.off_leafd + pidx * JM + c];
       *po.d() = dsum;
       *po.u() = u;
     }
@@ -308,10 +310,10 @@ __global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap
   double* S = slice(P, th);
   Post pp = post_of(P, S, m - 1, pidx);
   // children with observations below them (the others contribute zero)
-  int64_t ch[8];
+  int64_t ch[16];
   int nch = 0;
-  for (int c = 0; c < P.J; ++c)
-    if (post_active(P, m, pidx * P.J + c)) ch[nch++] = pidx * P.J + c;
+  for (int c = 0; c < P.Jl[m]; ++c)
+    if (post_active(P, m, pidx * P.Jl[m] + c)) ch[nch++] = pidx * P.Jl[m] + c;
   Acc acc;
   acc_zero(acc);
   for (int c = 0; c < nch; ++c) acc_load(acc, post_of(P, S, m, ch[c]).A(k, l), T, true);

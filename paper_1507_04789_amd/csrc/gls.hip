@@ -52,15 +52,16 @@ __global__ __launch_bounds__(NT) void k_gls_leaf(DevPlan P, int R, TaskMap tm) {
   double* G = gls_of(P, S, M - 1, pidx);
   const double* Yk = S + P.off_y + (int64_t)k * P.plane;
   const double* Yz = S + P.off_y + (int64_t)M * P.plane;
+  const int JM = P.Jl[M];
   int nsg = 0;
-  for (int c = 0; c < P.J; ++c) {
-    const int64_t leaf = pidx * P.J + c;
+  for (int c = 0; c < JM; ++c) {
+    const int64_t leaf = pidx * JM + c;
     nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
   Acc acc;
   acc_zero(acc);
   gemm_segs2(acc, nsg, [&](int sg) {
-    int64_t leaf = pidx * P.J;
+    int64_t leaf = pidx * JM;
     int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
     while (sg >= nbl) {
       sg -= nbl;
@@ -120,10 +121,10 @@ __global__ __launch_bounds__(NT) void k_gls_reduce(DevPlan P, int m, int R, Task
   const int64_t pidx = P.act_post[P.act_post_off[m - 1] + tk0 / (m + 1)];
   const int k = (int)(tk0 % (m + 1));
   double* S = slice(P, 0);
-  int64_t ch[8];
+  int64_t ch[16];
   int nch = 0;
-  for (int c = 0; c < P.J; ++c)
-    if (post_active(P, m, pidx * P.J + c)) ch[nch++] = pidx * P.J + c;
+  for (int c = 0; c < P.Jl[m]; ++c)
+    if (post_active(P, m, pidx * P.Jl[m] + c)) ch[nch++] = pidx * P.Jl[m] + c;
   double* GP = gls_of(P, S, m - 1, pidx);
   Acc acc;
   acc_zero(acc);
@@ -238,7 +239,9 @@ hipError_t launch_gls_leaf(const mra_plan_s& H, const DevPlan& P, int64_t q0, in
   Runner run{P, 1, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int M = P.M;
   const int64_t nq = (int64_t)H.reduce_order.size();
-  const double f = nq > 0 ? 2.0 * (double)P.n * ((double)M * P.r + R) * R * (double)(q1 - q0) / (double)nq : 0.0;
+  double rs = 0.0;
+  for (int l = 0; l < M; ++l) rs += P.rl[l];
+  const double f = nq > 0 ? 2.0 * (double)P.n * (rs + R) * R * (double)(q1 - q0) / (double)nq : 0.0;
   run.range("gls_leaf", -1, f, M + 1, k_gls_leaf, q0 * (M + 1), q1 * (M + 1), R);
   return hipGetLastError();
 }

@@ -340,7 +340,7 @@ __device__ void row_sweep_reverse(const DevPlan& P, double* S, const CovP& c, co
     __syncthreads();
     acc_zero(acc);
     gemm_lds_a(acc, lds, Pa + (l + 1) * TT, T, true, 1.0, lds + LDS_DOUBLES, mr);
-    acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.r, c, false, g);
+    acc_cov_contract(acc, X, nx, knots_of(P, l, al), P.rl[l], c, false, g);
     acc_store(acc, Rl, T);
     __syncthreads();
   }
@@ -400,13 +400,14 @@ __global__ __launch_bounds__(NT) void k_rT_leaf(DevPlan P, TaskMap tm) {
   const double* Wh = S + P.off_wobs + (int64_t)k * P.plane;
   Acc acc;
   acc_zero(acc);
+  const int JM = P.Jl[M];
   int nsg = 0;
-  for (int cc = 0; cc < P.J; ++cc) {
-    const int64_t leaf = pidx * P.J + cc;
+  for (int cc = 0; cc < JM; ++cc) {
+    const int64_t leaf = pidx * JM + cc;
     nsg += (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
   }
   gemm_segs2(acc, nsg, [&](int sg) {
-    int64_t leaf = pidx * P.J;
+    int64_t leaf = pidx * JM;
     int nbl = (int)((P.leaf_poff[leaf + 1] - P.leaf_poff[leaf]) / T);
     while (sg >= nbl) {
       sg -= nbl;
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
   symmetrize(sc);                                        // Wbar^m
   acc_load(acc, sc, T);
   double g[3] = {0.0, 0.0, 0.0};
-  acc_cov_contract(acc, X, P.r, X, P.r, c, false, g);
+  acc_cov_contract(acc, X, P.rl[m], X, P.rl[m], c, false, g);
   // W^-bar^k = -Tsum^{m,k} - 2 Wbar^m W^^k_R, k < m
   for (int k = 0; k < m; ++k) {
     acc_load(acc, gr.Tsum(m, k), T);
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
     acc_store(acc, gr.Wbar(k), T);
   }
   __syncthreads();
-  row_sweep_reverse(P, S, c, X, P.r, gr.Wbar(0), TT, m, i, g, lds, [&](Acc& acc, int l) { acc_load(acc, gr.Wbar(l), T); },
+  row_sweep_reverse(P, S, c, X, P.rl[m], gr.Wbar(0), TT, m, i, g, lds, [&](Acc& acc, int l) { acc_load(acc, gr.Wbar(l), T); },
                     0, [&](int, int) { return Seg{}; });
   write_partial(P, S, P.n_sig_tiles + P.n_row_tasks + P.reg_base[m] + i, g, red);
 }
@@ -499,10 +500,10 @@ __global__ __launch_bounds__(NT, 3) void k_rT(DevPlan P, int m, TaskMap tm) {
   int l, k;
   kl_split((int)(gid % nkl), l, k);
   double* S = slice(P, th);
-  int64_t ch[8];       // children with observations below them
+  int64_t ch[16];      // children with observations below them
   int nch = 0;
-  for (int c = 0; c < P.J; ++c)
-    if (post_active(P, m, pidx * P.J + c)) ch[nch++] = pidx * P.J + c;
+  for (int c = 0; c < P.Jl[m]; ++c)
+    if (post_active(P, m, pidx * P.Jl[m] + c)) ch[nch++] = pidx * P.Jl[m] + c;
   Acc acc;
   acc_zero(acc);
   for (int cc = 0; cc < nch; ++cc) acc_load(acc, grad_of(P, S, m, ch[cc]).Tsum(l, k), T, true);

@@ -2,11 +2,18 @@
 // assignment, padded leaf-sorted storage, arena layout and task lists.
 //
 // Partition rules (fixed so that independent implementations agree bit for
-// bit): d = 2, J = 4 splits each box at 0.5*(a+b) per axis, child
-// 2*[y >= ymid] + [x >= xmid]; d = 1 splits at a + ((b-a)*j)/J and the child
-// is the number of split points <= x; J = 1 keeps the box.  Default knots:
-// cell-centred g x g grid (d = 2, g = sqrt(r)), x_i = a + ((b-a)*(2i+1))/(2g),
-// index iy*g + ix; d = 1: x_i = a + ((b-a)*(2i+1))/(2r).
+// bit).  Every region of level m - 1 has J_m children.  A split into J is a
+// g_x x g_y grid: d = 1: g_x = J; d = 2: J = 1, 2, 4, 8, 16 as 1x1, 2x1, 2x2,
+// 4x2, 4x4 with the larger count along the longer side (x on ties).  The box
+// is cut along y into g_y slabs, then every slab along x into g_x cells;
+// child iy * g_x + ix, iy the number of y split values <= y, ix that of the
+// slab's x split values <= x.  Split values of [a, b] into g parts:
+// equal-area a + ((b - a) k) / g (2-D two-way splits at 0.5 (a + b)), or,
+// adaptive, quantiles of the observations in the region (slab):
+// 0.5 (v[i-1] + v[i]) with v sorted and i = (k len(v)) / g, equal parts when
+// fewer than g observations.  Default knots: cell-centred g x g grid (d = 2,
+// g = sqrt(r_m)), x_i = a + ((b-a)*(2i+1))/(2g), index iy*g + ix; d = 1:
+// x_i = a + ((b-a)*(2i+1))/(2 r_m).
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -20,47 +27,84 @@ struct Box {
   double a[2], b[2];
 };
 
-Box child_box(const Box& p, int j, int d, int J) {
+// split of one region into g_x x g_y children
+struct Split {
+  int gx = 1, gy = 1;
+  double ys[3] = {};      // g_y - 1 y split values
+  double xs[4][3] = {};   // per slab: g_x - 1 x split values
+};
+
+bool grid_shape(int d, int J, const Box& box, int& gx, int& gy) {
+  if (d == 1) {
+    gx = J;
+    gy = 1;
+    return J >= 1 && J <= 16;
+  }
+  const bool wide = (box.b[0] - box.a[0]) >= (box.b[1] - box.a[1]);
+  switch (J) {
+    case 1: gx = gy = 1; return true;
+    case 4: gx = gy = 2; return true;
+    case 16: gx = gy = 4; return true;
+    case 2: gx = wide ? 2 : 1; gy = wide ? 1 : 2; return true;
+    case 8: gx = wide ? 4 : 2; gy = wide ? 2 : 4; return true;
+    default: return false;
+  }
+}
+
+// split values of [a, b] into g parts: quantiles of v when it holds at least
+// g values (v is sorted here), equal parts otherwise
+void split_values(double a, double b, int g, int d, std::vector<double>* v, double* out) {
+  if (v && (int64_t)v->size() >= g) {
+    std::sort(v->begin(), v->end());
+    const int64_t n = (int64_t)v->size();
+    for (int k = 1; k < g; ++k) {
+      const int64_t i = (k * n) / g;
+      out[k - 1] = 0.5 * ((*v)[i - 1] + (*v)[i]);
+    }
+    return;
+  }
+  for (int k = 1; k < g; ++k)
+    out[k - 1] = (d == 2 && g == 2) ? 0.5 * (a + b) : a + ((b - a) * (double)k) / (double)g;
+}
+
+int child_index(const Split& s, const double* x, int d) {
+  int iy = 0, ix = 0;
+  if (d == 2)
+    for (int k = 0; k < s.gy - 1; ++k)
+      if (x[1] >= s.ys[k]) ++iy;
+  for (int k = 0; k < s.gx - 1; ++k)
+    if (x[0] >= s.xs[iy][k]) ++ix;
+  return iy * s.gx + ix;
+}
+
+Box child_box(const Box& p, const Split& s, int j, int d) {
   Box c = p;
-  if (J == 1) return c;
+  const int iy = j / s.gx, ix = j % s.gx;
   if (d == 2) {
-    int bx = j & 1, by = j >> 1;
-    double xm = 0.5 * (p.a[0] + p.b[0]);
-    double ym = 0.5 * (p.a[1] + p.b[1]);
-    if (bx) c.a[0] = xm; else c.b[0] = xm;
-    if (by) c.a[1] = ym; else c.b[1] = ym;
-    return c;
+    c.a[1] = iy == 0 ? p.a[1] : s.ys[iy - 1];
+    c.b[1] = iy == s.gy - 1 ? p.b[1] : s.ys[iy];
   }
-  double a = p.a[0], b = p.b[0];
-  c.a[0] = (j == 0) ? a : a + ((b - a) * (double)j) / (double)J;
-  c.b[0] = (j == J - 1) ? b : a + ((b - a) * (double)(j + 1)) / (double)J;
+  c.a[0] = ix == 0 ? p.a[0] : s.xs[iy][ix - 1];
+  c.b[0] = ix == s.gx - 1 ? p.b[0] : s.xs[iy][ix];
   return c;
 }
 
-int child_of(const Box& p, const double* x, int d, int J) {
-  if (J == 1) return 0;
-  if (d == 2) {
-    double xm = 0.5 * (p.a[0] + p.b[0]);
-    double ym = 0.5 * (p.a[1] + p.b[1]);
-    return 2 * (x[1] >= ym ? 1 : 0) + (x[0] >= xm ? 1 : 0);
-  }
-  double a = p.a[0], b = p.b[0];
-  int c = 0;
-  for (int k = 1; k < J; ++k)
-    if (x[0] >= a + ((b - a) * (double)k) / (double)J) ++c;
-  return c;
+bool inside(const double* x, int d, const double* lo, const double* hi) {
+  for (int a = 0; a < d; ++a)
+    if (!std::isfinite(x[a]) || x[a] < lo[a] || x[a] > hi[a]) return false;
+  return true;
 }
 
-// leaf index of every point; returns false if a point is outside or not finite
-bool assign_leaves(const std::vector<std::vector<Box>>& boxes, const double* pts, int64_t n, int d, int J, int M,
-                   const double* lo, const double* hi, std::vector<int64_t>& leaf) {
+// leaf index of every point by descending the splits; false if a point is
+// outside the box or not finite
+bool assign_leaves(const std::vector<std::vector<Split>>& splits, const std::vector<int32_t>& Jl, const double* pts,
+                   int64_t n, int d, int M, const double* lo, const double* hi, std::vector<int64_t>& leaf) {
   leaf.assign(n, 0);
   for (int64_t p = 0; p < n; ++p) {
     const double* x = pts + p * d;
-    for (int a = 0; a < d; ++a)
-      if (!std::isfinite(x[a]) || x[a] < lo[a] || x[a] > hi[a]) return false;
+    if (!inside(x, d, lo, hi)) return false;
     int64_t i = 0;
-    for (int m = 0; m < M; ++m) i = i * J + child_of(boxes[m][i], x, d, J);
+    for (int m = 0; m < M; ++m) i = i * Jl[m + 1] + child_index(splits[m][i], x, d);
     leaf[p] = i;
   }
   return true;
@@ -85,51 +129,109 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
                       const double* h_knots, mra_plan_s* P) {
   if (!cfg || (!h_locs && n > 0) || n < 1 || n_pred < 0 || (n_pred > 0 && !h_pred)) return MRA_EINVAL;
   const int d = cfg->d, M = cfg->M, J = cfg->J, r = cfg->r;
-  if (d < 1 || d > 2 || M < 0 || M >= MAXL || r < 1 || r > T || cfg->max_theta < 1) return MRA_EINVAL;
+  if (d < 1 || d > 2 || M < 0 || M >= MAXL || cfg->max_theta < 1) return MRA_EINVAL;
   if (cfg->flags & ~(MRA_SYNC | MRA_PLAIN | MRA_GRAPH | MRA_NO_GRAD | MRA_CHECKPOINT | MRA_JOINT)) return MRA_EINVAL;
-  if (cfg->chunks < 0) return MRA_EINVAL;
-  if (d == 2 && J != 1 && J != 4) return MRA_EINVAL;
-  if (d == 1 && (J < 1 || J > 8)) return MRA_EINVAL;
+  if (cfg->chunks < 0 || (cfg->adaptive != 0 && cfg->adaptive != 1)) return MRA_EINVAL;
   if (cfg->cov != MRA_COV_EXPONENTIAL && cfg->cov != MRA_COV_MATERN32) return MRA_EINVAL;
   for (int a = 0; a < d; ++a)
     if (!(cfg->lo[a] < cfg->hi[a]) || !std::isfinite(cfg->lo[a]) || !std::isfinite(cfg->hi[a])) return MRA_EINVAL;
-  int g = 0;
-  if (!h_knots && d == 2) {
-    g = (int)std::lround(std::sqrt((double)r));
-    if (g * g != r) return MRA_EINVAL;
+  // children and knots per level
+  std::vector<int32_t> Jl(M + 1, 1), rl(std::max(M, 1), r);
+  for (int m = 1; m <= M; ++m) Jl[m] = cfg->J_level[m - 1] > 0 ? cfg->J_level[m - 1] : J;
+  for (int m = 0; m < M; ++m) rl[m] = cfg->r_level[m] > 0 ? cfg->r_level[m] : r;
+  for (int m = 1; m <= M; ++m) {
+    if (d == 2 && Jl[m] != 1 && Jl[m] != 2 && Jl[m] != 4 && Jl[m] != 8 && Jl[m] != 16) return MRA_EINVAL;
+    if (d == 1 && (Jl[m] < 1 || Jl[m] > 16)) return MRA_EINVAL;
   }
+  for (int m = 0; m < M; ++m) {
+    if (rl[m] < 1 || rl[m] > T) return MRA_EINVAL;
+    if (!h_knots && d == 2) {
+      const int g = (int)std::lround(std::sqrt((double)rl[m]));
+      if (g * g != rl[m]) return MRA_EINVAL;
+    }
+  }
+  if (M == 0 && (r < 1 || r > T)) return MRA_EINVAL;
   P->cfg = *cfg;
   P->d = d; P->M = M; P->J = J; P->r = r; P->n = n; P->n_pred = n_pred;
+  P->Jl = Jl;
+  P->rl = rl;
   P->side_solves = M + 2;   // leaf solves forked once the forward recursion is enqueued
   // levels
   P->nreg.assign(M + 1, 1);
-  for (int m = 1; m <= M; ++m) P->nreg[m] = P->nreg[m - 1] * J;
+  for (int m = 1; m <= M; ++m) P->nreg[m] = P->nreg[m - 1] * Jl[m];
   P->reg_base.assign(M + 1, 0);
   for (int m = 1; m <= M; ++m) P->reg_base[m] = P->reg_base[m - 1] + P->nreg[m - 1];
   const int64_t n_internal = P->reg_base[M];
   const int64_t n_leaves = P->nreg[M];
-  // boxes
+  if (n_leaves > ((int64_t)1 << 31) - 1) return MRA_EINVAL;
+  for (int a = 0; a < d; ++a)
+    for (int64_t p = 0; p < n; ++p)
+      if (!inside(h_locs + p * d, d, cfg->lo, cfg->hi)) return MRA_EINVAL;
+  // boxes and splits, level by level; adaptive splits use the observations
+  // of each region (grouped by a counting sort of their current region)
   std::vector<std::vector<Box>> boxes(M + 1);
+  std::vector<std::vector<Split>> splits(M);
   Box root;
   for (int a = 0; a < 2; ++a) { root.a[a] = a < d ? cfg->lo[a] : 0.0; root.b[a] = a < d ? cfg->hi[a] : 0.0; }
   boxes[0].push_back(root);
+  const bool adaptive = cfg->adaptive == 1;
+  std::vector<int64_t> cur(n, 0), start, byreg;
   for (int m = 0; m < M; ++m) {
+    const int64_t nr = P->nreg[m];
+    const int J1 = Jl[m + 1];
+    if (adaptive) {
+      start.assign(nr + 1, 0);
+      for (int64_t p = 0; p < n; ++p) start[cur[p] + 1]++;
+      for (int64_t i = 0; i < nr; ++i) start[i + 1] += start[i];
+      byreg.assign(n, 0);
+      std::vector<int64_t> pos(start.begin(), start.end() - 1);
+      for (int64_t p = 0; p < n; ++p) byreg[pos[cur[p]]++] = p;
+    }
+    splits[m].resize(nr);
     boxes[m + 1].resize(P->nreg[m + 1]);
-    for (int64_t i = 0; i < P->nreg[m]; ++i)
-      for (int j = 0; j < J; ++j) boxes[m + 1][i * J + j] = child_box(boxes[m][i], j, d, J);
+    std::vector<double> vy, vx;
+    for (int64_t i = 0; i < nr; ++i) {
+      const Box& bx = boxes[m][i];
+      Split& sp = splits[m][i];
+      if (!grid_shape(d, J1, bx, sp.gx, sp.gy)) return MRA_EINVAL;
+      const int64_t p0 = adaptive ? start[i] : 0, p1 = adaptive ? start[i + 1] : 0;
+      if (d == 2) {
+        vy.clear();
+        for (int64_t q = p0; q < p1; ++q) vy.push_back(h_locs[byreg[q] * d + 1]);
+        split_values(bx.a[1], bx.b[1], sp.gy, d, adaptive ? &vy : nullptr, sp.ys);
+      }
+      for (int iy = 0; iy < sp.gy; ++iy) {
+        vx.clear();
+        for (int64_t q = p0; q < p1; ++q) {
+          const double* x = h_locs + byreg[q] * d;
+          int cy = 0;
+          if (d == 2)
+            for (int k = 0; k < sp.gy - 1; ++k)
+              if (x[1] >= sp.ys[k]) ++cy;
+          if (cy == iy) vx.push_back(x[0]);
+        }
+        split_values(bx.a[0], bx.b[0], sp.gx, d, adaptive ? &vx : nullptr, sp.xs[iy]);
+      }
+      for (int j = 0; j < J1; ++j) boxes[m + 1][i * J1 + j] = child_box(bx, sp, j, d);
+    }
+    for (int64_t p = 0; p < n; ++p) cur[p] = cur[p] * J1 + child_index(splits[m][cur[p]], h_locs + p * d, d);
   }
-  // knots
-  P->knots.assign((size_t)n_internal * r * d, 0.0);
+  // knots: r_m x d per region of level m, level-major
+  P->knot_off.assign(M + 1, 0);
+  for (int m = 0; m < M; ++m) P->knot_off[m + 1] = P->knot_off[m] + P->nreg[m] * rl[m] * d;
+  P->knots.assign((size_t)P->knot_off[M], 0.0);
   if (h_knots) {
     for (size_t q = 0; q < P->knots.size(); ++q) {
       if (!std::isfinite(h_knots[q])) return MRA_EINVAL;
       P->knots[q] = h_knots[q];
     }
   } else {
-    for (int m = 0; m < M; ++m)
+    for (int m = 0; m < M; ++m) {
+      const int rm = rl[m];
+      const int g = d == 2 ? (int)std::lround(std::sqrt((double)rm)) : rm;
       for (int64_t i = 0; i < P->nreg[m]; ++i) {
         const Box& b = boxes[m][i];
-        double* kn = P->knots.data() + (size_t)(P->reg_base[m] + i) * r * d;
+        double* kn = P->knots.data() + P->knot_off[m] + (size_t)i * rm * d;
         if (d == 2) {
           for (int iy = 0; iy < g; ++iy)
             for (int ix = 0; ix < g; ++ix) {
@@ -137,18 +239,22 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
               kn[(iy * g + ix) * 2 + 1] = b.a[1] + ((b.b[1] - b.a[1]) * (double)(2 * iy + 1)) / (double)(2 * g);
             }
         } else {
-          for (int k = 0; k < r; ++k)
-            kn[k] = b.a[0] + ((b.b[0] - b.a[0]) * (double)(2 * k + 1)) / (double)(2 * r);
+          for (int k = 0; k < rm; ++k)
+            kn[k] = b.a[0] + ((b.b[0] - b.a[0]) * (double)(2 * k + 1)) / (double)(2 * rm);
         }
       }
+    }
   }
   P->knot_xy.assign((size_t)std::max<int64_t>(n_internal, 1) * T * 2, 0.0);
-  for (int64_t q = 0; q < n_internal; ++q)
-    for (int k = 0; k < r; ++k)
-      for (int a = 0; a < d; ++a) P->knot_xy[(q * T + k) * 2 + a] = P->knots[(q * r + k) * d + a];
+  for (int m = 0; m < M; ++m)
+    for (int64_t i = 0; i < P->nreg[m]; ++i) {
+      const int64_t q = P->reg_base[m] + i;
+      const double* kn = P->knots.data() + P->knot_off[m] + (size_t)i * rl[m] * d;
+      for (int k = 0; k < rl[m]; ++k)
+        for (int a = 0; a < d; ++a) P->knot_xy[(q * T + k) * 2 + a] = kn[k * d + a];
+    }
   // observations
-  std::vector<int64_t> leaf;
-  if (!assign_leaves(boxes, h_locs, n, d, J, M, cfg->lo, cfg->hi, leaf)) return MRA_EINVAL;
+  std::vector<int64_t> leaf(cur);
   sort_by_leaf(leaf, n_leaves, P->perm, P->leaf_off);
   P->leaf_n.assign(n_leaves, 0);
   P->leaf_poff.assign(n_leaves + 1, 0);
@@ -180,7 +286,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     }
   // prediction locations
   std::vector<int64_t> pleaf;
-  if (n_pred > 0 && !assign_leaves(boxes, h_pred, n_pred, d, J, M, cfg->lo, cfg->hi, pleaf)) return MRA_EINVAL;
+  if (n_pred > 0 && !assign_leaves(splits, Jl, h_pred, n_pred, d, M, cfg->lo, cfg->hi, pleaf)) return MRA_EINVAL;
   sort_by_leaf(pleaf, n_leaves, P->pperm, P->pleaf_off);
   P->pleaf_n.assign(n_leaves, 0);
   P->pleaf_poff.assign(n_leaves + 1, 0);
@@ -203,7 +309,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   // with about equal padded rows; a single chunk otherwise
   {
     const int64_t nparent = M > 0 ? P->nreg[M - 1] : 1;
-    const int64_t per = M > 0 ? J : n_leaves;   // leaves per level-(M-1) region
+    const int64_t per = M > 0 ? Jl[M] : n_leaves;   // leaves per level-(M-1) region
     int64_t K = 1;
     if ((cfg->flags & MRA_CHECKPOINT) && M > 0) K = std::min<int64_t>(cfg->chunks > 0 ? cfg->chunks : 8, nparent);
     P->chunk_leaf.assign(1, 0);
@@ -327,9 +433,9 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
       obs_below[m].assign(P->nreg[m], 0);
       prd_below[m].assign(P->nreg[m], 0);
       for (int64_t i = 0; i < P->nreg[m]; ++i)
-        for (int c = 0; c < J; ++c) {
-          obs_below[m][i] += co[i * J + c];
-          prd_below[m][i] += cp[i * J + c];
+        for (int c = 0; c < Jl[m + 1]; ++c) {
+          obs_below[m][i] += co[i * Jl[m + 1] + c];
+          prd_below[m][i] += cp[i * Jl[m + 1] + c];
         }
       co = obs_below[m];
       cp = prd_below[m];
@@ -365,13 +471,13 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
     const int64_t np = P->nreg[M - 1];
     std::vector<int64_t> maxnb(np, 0);
     for (int64_t q = 0; q < np; ++q)
-      for (int c = 0; c < J; ++c) {
-        const int64_t lf = q * J + c;
+      for (int c = 0; c < Jl[M]; ++c) {
+        const int64_t lf = q * Jl[M] + c;
         maxnb[q] = std::max<int64_t>(maxnb[q], (P->leaf_poff[lf + 1] - P->leaf_poff[lf]) / T);
       }
     P->reduce_order.assign(P->act_post.begin() + P->act_post_off[M - 1], P->act_post.begin() + P->act_post_off[M]);
     std::stable_sort(P->reduce_order.begin(), P->reduce_order.end(), [&](int32_t x, int32_t y) {
-      const int cx = chunk_of[(int64_t)x * J], cy = chunk_of[(int64_t)y * J];
+      const int cx = chunk_of[(int64_t)x * Jl[M]], cy = chunk_of[(int64_t)y * Jl[M]];
       if (cx != cy) return cx < cy;
       return maxnb[x] < maxnb[y];
     });
@@ -385,9 +491,9 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   P->ck_actq.assign(P->nchunks + 1, 0);
   if (M > 0) {
     for (size_t q = 0; q < P->reduce_order.size(); ++q)
-      P->ck_red[chunk_of[(int64_t)P->reduce_order[q] * J] + 1] = (int64_t)q + 1;
+      P->ck_red[chunk_of[(int64_t)P->reduce_order[q] * Jl[M]] + 1] = (int64_t)q + 1;
     for (int64_t q = P->act_post_off[M - 1]; q < P->act_post_off[M]; ++q)
-      P->ck_actq[chunk_of[(int64_t)P->act_post[q] * J] + 1] = q - P->act_post_off[M - 1] + 1;
+      P->ck_actq[chunk_of[(int64_t)P->act_post[q] * Jl[M]] + 1] = q - P->act_post_off[M - 1] + 1;
   }
   for (int c = 1; c <= P->nchunks; ++c) {
     P->ck_red[c] = std::max(P->ck_red[c], P->ck_red[c - 1]);
@@ -434,7 +540,11 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   // ---- work arena layout (doubles per theta slice) ----
   DevPlan& D = P->dp;
   D = DevPlan{};
-  D.d = d; D.M = M; D.J = J; D.r = r; D.cov = cfg->cov;
+  D.d = d; D.M = M; D.cov = cfg->cov;
+  for (int m = 0; m < MAXL; ++m) {
+    D.Jl[m] = m <= M ? Jl[m] : 1;
+    D.rl[m] = m < M ? rl[m] : 0;
+  }
   D.n_sig_tasks = (int64_t)P->sig_tasks.size() / 3;
   D.n_sig_tiles = P->n_sig_tiles;
   D.n_row_tasks = (int64_t)P->row_tasks.size() / 2;
@@ -503,6 +613,8 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   L.theta_stride = w;
 
   // large-leaf counts and factorisation flop prefix sums in fac_tasks order
+  double rs_all = 0.0;
+  for (int m = 0; m < M; ++m) rs_all += rl[m];
   {
     const int64_t nf = (int64_t)P->fac_tasks.size();
     for (int t = 0; t < 16; ++t) P->nbig_thr[t] = 0;
@@ -515,7 +627,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
         if (nb >= t) ++P->nbig_thr[t];
       const double nr = P->leaf_n[lf];
       P->fac_flops_pre[q + 1] = P->fac_flops_pre[q] + nr * nr * nr / 3.0;
-      P->trsm_flops_pre[q + 1] = P->trsm_flops_pre[q] + nr * nr * ((double)M * r + 1);
+      P->trsm_flops_pre[q + 1] = P->trsm_flops_pre[q] + nr * nr * (rs_all + 1);
     }
   }
 
@@ -524,42 +636,52 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   // triangular solves and products count r^2 per right-hand side column.
   PhaseFlops& F = P->pf;
   F = PhaseFlops{};
-  const double rr = r, Mr = M * rr;
+  // chain knots above level m: S[m] = sum_{k<m} r_k; rs = S[M]
+  std::vector<double> Sk(M + 1, 0.0);
+  for (int m = 0; m < M; ++m) Sk[m + 1] = Sk[m] + rl[m];
+  const double rs = Sk[M];
   for (int m = 0; m < M; ++m) {
     const double Rp = (double)P->nact_prior(m), R = (double)P->nact_post(m);   // active regions
-    double pr = rr * rr * (m * rr) + rr * rr * rr / 3.0;                  // SYRK + POTRF
-    for (int l = 0; l < m; ++l) pr += 2.0 * rr * rr * (l * rr) + rr * rr * rr;   // GEMM + TRSM
+    const double rm = rl[m], Sm = Sk[m];
+    double pr = rm * rm * Sm + rm * rm * rm / 3.0;                               // SYRK + POTRF
+    for (int l = 0; l < m; ++l) pr += 2.0 * rm * rl[l] * Sk[l] + rm * rl[l] * rl[l];   // GEMM + TRSM
     F.prior[m] = Rp * pr;
-    const double k = m * rr + 1;
-    F.post[m] = R * (rr * rr * rr / 3.0 + rr * rr * k);                        // POTRF + TRSM of [A^{m,<m} | w^m]
+    const double k = Sm + 1;
+    F.post[m] = R * (rm * rm * rm / 3.0 + rm * rm * k);                          // POTRF + TRSM of [A^{m,<m} | w^m]
     // children of level m summed into level m-1: A~ = A - Z'Z per child
-    if (m > 0) F.post_reduce[m] = R * (m * rr) * (m * rr + 1) * rr + R * 2.0 * (m * rr) * rr;
+    if (m > 0) F.post_reduce[m] = R * Sm * (Sm + 1) * rm + R * 2.0 * Sm * rm;
     // reverse: V = Lt^{-T} Z, Xbar = 2 V Fbar, Pbar = -V Fbar V' - P^{-1}/2
-    F.rpost[m] = R * (rr * rr * k + 2.0 * rr * (m * rr) * (m * rr) + 2.0 * rr * rr * (m * rr) + rr * rr * rr);
+    F.rpost[m] = R * (rm * rm * k + 2.0 * rm * Sm * Sm + 2.0 * rm * rm * Sm + rm * rm * rm);
     // Cholesky adjoint (3 triangular products), -2 Wbar^m W^^k, reverse row sweep
-    double rp = 3.0 * rr * rr * rr + 2.0 * rr * rr * (m * rr);
-    for (int l = 0; l < m; ++l) rp += 2.0 * rr * rr * rr + 2.0 * rr * rr * (l * rr);
+    double rp = 3.0 * rm * rm * rm + 2.0 * rm * rm * Sm;
+    for (int l = 0; l < m; ++l) rp += 2.0 * rm * rl[l] * rl[l] + 2.0 * rm * rl[l] * Sk[l];
     F.rprior[m] = R * rp;
     // subtree sums of level m (children) into level m-1: Wbar^l' W^^k, k <= l < m
     double rt = 0.0;
-    for (int l = 0; l < m; ++l) rt += 2.0 * rr * rr * ((l + 1) * rr);
+    for (int l = 0; l < m; ++l) rt += 2.0 * rm * rl[l] * Sk[l + 1];
     F.rT[m] = R * rt;
+  }
+  double rows_sweep = 0.0, rows_rev = 0.0, rows_T = 0.0;   // per observation
+  for (int l = 0; l < M; ++l) {
+    rows_sweep += 2.0 * rl[l] * Sk[l] + (double)rl[l] * rl[l];
+    rows_rev += 2.0 * (double)rl[l] * rl[l] + 2.0 * rl[l] * (rs - Sk[l + 1]);
+    rows_T += 2.0 * rl[l] * Sk[l + 1];
   }
   for (int64_t i = 0; i < n_leaves; ++i) {
     const double nr = P->leaf_n[i];
     if (nr == 0) continue;
-    F.leaf_rows += nr * rr * rr * (double)(M * (M - 1) + M);   // rows of W^: GEMM + TRSM per level
-    F.sigma += nr * nr * Mr;                                   // Sigma_R (SYRK)
+    F.leaf_rows += nr * rows_sweep;                            // rows of W^: GEMM + TRSM per level
+    F.sigma += nr * nr * rs;                                   // Sigma_R (SYRK)
     F.potrf += nr * nr * nr / 3.0;
-    F.trsm += nr * nr * (Mr + 1);                              // L^{-1} [W^ | z]
-    F.leaf_reduce += nr * (Mr + 1) * (Mr + 1);                 // [W^ | z]' Sigma^{-1} [W^ | z]
-    F.rleaf_v += nr * nr * (Mr + 1);                           // L^{-T} Y
+    F.trsm += nr * nr * (rs + 1);                              // L^{-1} [W^ | z]
+    F.leaf_reduce += nr * (rs + 1) * (rs + 1);                 // [W^ | z]' Sigma^{-1} [W^ | z]
+    F.rleaf_v += nr * nr * (rs + 1);                           // L^{-T} Y
     F.rleaf_linv += nr * nr * nr / 3.0;                        // L^{-1}
-    F.rleaf_q += 2.0 * nr * (Mr + 1) * (Mr + 1);               // V Fbar
-    F.rleaf_sbar += nr * nr * (Mr + 1) + nr * nr * nr / 3.0;   // -Q V' - Sigma^{-1}/2 (lower half)
-    F.rleaf_wbar += 2.0 * nr * nr * Mr;                        // Sigma-bar W^
-    F.rrows += nr * rr * rr * (double)(2 * M + M * (M - 1));   // Wbar^l = W^bar L^{-1}, W^-bar updates
-    F.rT_leaf += nr * rr * rr * (double)(M * (M + 1));         // Wbar^l' W^^k, k <= l
+    F.rleaf_q += 2.0 * nr * (rs + 1) * (rs + 1);               // V Fbar
+    F.rleaf_sbar += nr * nr * (rs + 1) + nr * nr * nr / 3.0;   // -Q V' - Sigma^{-1}/2 (lower half)
+    F.rleaf_wbar += 2.0 * nr * nr * rs;                        // Sigma-bar W^
+    F.rrows += nr * rows_rev;                                  // Wbar^l = W^bar L^{-1}, W^-bar updates
+    F.rT_leaf += nr * rows_T;                                  // Wbar^l' W^^k, k <= l
   }
   double fl = F.leaf_rows + F.sigma + F.potrf + F.trsm + F.leaf_reduce;
   double rv = F.rleaf_v + F.rleaf_linv + F.rleaf_q + F.rleaf_sbar + F.rleaf_wbar + F.rrows + F.rT_leaf;
@@ -573,10 +695,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
   for (int64_t i = 0; i < n_leaves; ++i) {
     const double np = P->pleaf_n[i], nr = P->leaf_n[i];
     if (np == 0) continue;
-    fp += np * rr * rr * (double)(M * (M - 1) + M);     // U^ rows
-    fp += 2.0 * np * nr * Mr + np * nr * nr;             // L^M and E = L^M L^{-T}
-    fp += 2.0 * np * nr * Mr;                            // B~^M
-    for (int l = 0; l < M; ++l) fp += np * (rr * rr + 2.0 * rr * rr * l);
+    fp += np * rows_sweep;                               // U^ rows
+    fp += 2.0 * np * nr * rs + np * nr * nr;             // L^M and E = L^M L^{-T}
+    fp += 2.0 * np * nr * rs;                            // B~^M
+    for (int l = 0; l < M; ++l) fp += np * ((double)rl[l] * rl[l] + 2.0 * rl[l] * Sk[l]);
   }
   F.predict = fp;
   P->flops_predict = fp;

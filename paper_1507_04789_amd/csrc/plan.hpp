@@ -40,7 +40,9 @@ struct mra_plan_s {
   mra_config cfg;
   int d, M, J, r;
   int64_t n, n_pred;
-  std::vector<double> knots;          // (sum_{m<M} J^m) x r x d, as built
+  std::vector<double> knots;          // r_m x d per region of level m < M, level-major, as built
+  std::vector<int64_t> knot_off;      // [M + 1] first entry of level m in knots
+  std::vector<int32_t> Jl, rl;        // children per region of level m - 1; knots per region of level m
   std::vector<int64_t> nreg, reg_base;
   std::vector<int64_t> perm;          // leaf order -> original index
   std::vector<int64_t> leaf_off;      // CSR offsets (unpadded)

@@ -38,9 +38,28 @@ def test_geometry_matches_oracle(d, J, M, r, n):
     assert (perm == og.perm).all()
     assert (off == og.offsets).all()
     for m in range(M):
-        base = sum(J ** q for q in range(m))
-        got = kn[base:base + J ** m]
-        assert np.array_equal(got, og.knots[m])   # bitwise
+        assert np.array_equal(kn[m], og.knots[m])   # bitwise
+
+
+@pytest.mark.parametrize("Jl,rl,adaptive", [((2, 2, 4, 8), (16, 9, 9, 4), False), ((2, 2, 4, 8), (16, 9, 9, 4), True),
+                                            ((4, 16), (64, 16), True), ((8, 4, 2), (4, 4, 4), True)])
+def test_mixed_and_adaptive_geometry_matches_oracle(Jl, rl, adaptive):
+    """Level-dependent J_m, r_m and adaptive splits: the library's partition
+    (leaf order and CSR offsets) and default knots equal the oracle's bit for
+    bit, also for prediction locations (their leaves follow the same splits)."""
+    w = wl.clustered(n=20000, M=len(Jl))
+    M = len(Jl)
+    pred = np.random.default_rng(4).random((500, 2))
+    p = Plan(w.locs, M=M, J=4, r=4, cov=w.cov, J_levels=Jl, r_levels=rl, adaptive=adaptive, pred=pred)
+    perm, off, kn = p.geometry()
+    og = Geometry(w.locs, 2, M, 4, 4, J_levels=Jl, r_levels=rl, adaptive=adaptive)
+    assert (perm == og.perm).all() and (off == og.offsets).all()
+    for m in range(M):
+        assert np.array_equal(kn[m], og.knots[m])
+    assert p.info["n_leaves"] == og.nreg[M]
+    if adaptive:   # flatter leaves than equal-area splits of the clustered scatter
+        eq = Geometry(w.locs, 2, M, 4, 4, J_levels=Jl, r_levels=rl)
+        assert np.diff(og.offsets).max() < np.diff(eq.offsets).max()
 
 
 def test_clustered_geometry_matches_oracle():
@@ -58,12 +77,12 @@ def test_explicit_knots_roundtrip():
     kn = [g0.random((4 ** m, 9, 2)) for m in range(2)]
     p = Plan(locs, M=2, J=4, r=9, cov="exponential", knots=kn)
     _, _, got = p.geometry()
-    assert np.array_equal(got, np.concatenate(kn))
+    assert all(np.array_equal(a, b) for a, b in zip(got, kn))
 
 
 @pytest.mark.parametrize("bad", [
     dict(M=3, J=4, r=15),          # default 2-D knots need a square r
-    dict(M=3, J=2, r=16),          # d = 2 needs J in {1, 4}
+    dict(M=3, J=3, r=16),          # d = 2 needs J in {1, 2, 4, 8, 16}
     dict(M=3, J=4, r=65),          # r above the tile
     dict(M=12, J=4, r=16),         # too many levels
 ])

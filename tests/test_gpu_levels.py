@@ -1,0 +1,100 @@
+"""Level-dependent J_m, r_m and data-adaptive splits on the GPU against the
+oracle: log-likelihood (1e-10 relative), gradient (1e-6 per component) and
+kriging (1e-10 entry by entry), with 2-D splits into 2, 4, 8 and 16
+children, knot counts from 1 to 64 per level, quantile splits of clustered
+data, and one dimension; plus the satellite application's J_m =
+(2, 2, 4, 8, 8, 16) at n = 2^18 with the properties that hold at any size
+(the scale identity and central differences)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mra, predict
+from oracle.geometry import Geometry
+from paper_1507_04789_amd import MRA_CHECKPOINT, MRA_SYNC, Plan
+from paper_1507_04789_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _th(s2, k, t2):
+    return np.array([math.log(s2), math.log(k), math.log(t2)])
+
+
+CASES = [
+    # name, n, J_levels, r_levels, adaptive, d, cov
+    ("halves_quads_eighths", 4096, (2, 2, 4, 8), (16, 9, 9, 4), False, 2, "matern32"),
+    ("adaptive_clustered", 8192, (4, 4, 4, 4), (16, 16, 16, 16), True, 2, "matern32"),
+    ("adaptive_mixed", 6000, (2, 8, 4), (36, 16, 9), True, 2, "exponential"),
+    ("sixteen_r64", 5000, (4, 16), (16, 64), False, 2, "matern32"),
+    ("one_dim_mixed", 900, (2, 3, 4), (3, 2, 1), True, 1, "exponential"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_levels_against_oracle(case):
+    name, n, Jl, rl, adaptive, d, kind = case
+    M = len(Jl)
+    g = np.random.default_rng(80 + M)
+    if name.startswith("adaptive_clustered"):
+        w = wl.clustered(n=n, M=M, r=16)
+        locs, z = w.locs, w.z
+    else:
+        locs = g.random((n, d))
+        if d == 2:
+            locs[: n // 3] = 0.2 + 0.1 * locs[: n // 3]     # a dense patch
+        z = g.standard_normal(n)
+    pred = g.random((300, d))
+    th = _th(1.1, 0.12, 0.03)
+    print("levels case %s n=%d J=%s r=%s adaptive=%s" % (name, n, Jl, rl, adaptive), flush=True)
+    geo = Geometry(locs, d, M, 4, 4, J_levels=Jl, r_levels=rl, adaptive=adaptive)
+    rll, rg, _ = mra.loglik(geo, z, kind, th, grad=True)
+    rmu, rvar = predict.predict(geo, z, kind, th, pred)
+    for flags in (MRA_SYNC, MRA_SYNC | MRA_CHECKPOINT):
+        p = Plan(locs, M=M, J=4, r=4, d=d, cov=kind, J_levels=Jl, r_levels=rl, adaptive=adaptive, pred=pred,
+                 flags=flags, chunks=2)
+        ll, gr = p.loglik_grad(z, th)
+        mu, var = p.predict(z, th)
+        ll, gr, mu, var = float(ll[0]), gr[0].cpu().numpy(), mu.cpu().numpy(), var.cpu().numpy()
+        assert abs(ll - rll) <= 1e-10 * abs(rll), (ll, rll)
+        assert (np.abs(gr - rg) <= 1e-6 * np.abs(rg)).all(), (gr, rg)
+        assert (np.abs(mu - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
+        assert (np.abs(var - rvar) <= 1e-10 * rvar + 1e-12 * math.exp(th[0])).all()
+
+
+def test_satellite_levels_full_size_properties():
+    """J_m = (2, 2, 4, 8, 8, 16) (16384 leaves) with 16 knots per region on
+    the clustered n = 2^18 data: the scale identity
+    loglik(s z; s^2 sigma^2, kappa, s^2 tau^2) = loglik(z) - n log s to 1e-10,
+    and the gradient against central differences of the GPU log-likelihood;
+    adaptive splits of the same levels flatten the leaf counts."""
+    w = wl.clustered()
+    Jl, rl = (2, 2, 4, 8, 8, 16), (16,) * 6
+    print("satellite levels n=%d J=%s r=16" % (len(w.z), Jl), flush=True)
+    for adaptive in (False, True):
+        p = Plan(w.locs, M=6, J=4, r=16, cov=w.cov, J_levels=Jl, r_levels=rl, adaptive=adaptive, flags=0)
+        assert p.info["n_leaves"] == 16384
+        p.bind("cuda:0")
+        z = torch.tensor(w.z, device="cuda:0")
+        th = torch.tensor(w.theta, dtype=torch.float64, device="cuda:0").reshape(1, 3)
+        ll, g = p.loglik_grad(z, th)
+        ll, g = float(ll[0]), g[0].cpu().numpy()
+        assert math.isfinite(ll) and np.isfinite(g).all()
+        s = 3.0
+        shift = torch.tensor([[2 * math.log(s), 0.0, 2 * math.log(s)]], dtype=torch.float64, device="cuda:0")
+        l2 = float(p.loglik(z * s, th + shift)[0])
+        assert abs(l2 - (ll - len(w.z) * math.log(s))) <= 1e-10 * abs(ll)
+        h = 1e-5
+        for a in range(3):
+            e = torch.zeros(1, 3, dtype=torch.float64, device="cuda:0")
+            e[0, a] = h
+            fd = (float(p.loglik(z, th + e)[0]) - float(p.loglik(z, th - e)[0])) / (2 * h)
+            assert abs(fd - g[a]) <= 1e-6 * abs(g[a]) + 2e-13 * abs(ll) / h, (a, fd, g[a])
+        if adaptive:
+            assert p.info["max_leaf"] < max_equal
+        else:
+            max_equal = p.info["max_leaf"]
+        del p
+        torch.cuda.empty_cache()
