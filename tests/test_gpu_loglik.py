@@ -131,6 +131,56 @@ def test_failure_reports_theta():
     assert abs(out[2] - ref) <= RTOL * abs(ref)
 
 
+def _last_failure(p):
+    import ctypes as C
+    from paper_1507_04789_amd import _lib
+    th, lv, rg = C.c_int32(), C.c_int32(), C.c_int64()
+    _lib.lib().mra_last_failure(p._h, C.byref(th), C.byref(lv), C.byref(rg), p._stream())
+    return th.value, lv.value, rg.value
+
+
+@pytest.mark.parametrize("case", ["huge_range_root", "duplicate_leaf_points"])
+def test_breakdown_matches_oracle(case):
+    """Singular inputs where the oracle's Cholesky raises LinAlgError: a range
+    so large that the root's K^{-1} is numerically rank one (failure at level
+    0, region 0), and 21 copies of one location in a leaf with a negligible
+    nugget (failure at level M, that leaf).  The library returns MRA_ENOTPD
+    and names the same parameter row, level and region; the other rows of
+    the batch keep their values."""
+    from numpy.linalg import LinAlgError
+    from paper_1507_04789_amd import _lib
+    g = np.random.default_rng(90)
+    locs = g.random((800, 2))
+    z = g.standard_normal(800)
+    geo = Geometry(locs, 2, 3, 4, 16)
+    bad = _th(1.0, math.exp(16.0), 0.01)
+    where = (0, 0)
+    if case == "duplicate_leaf_points":
+        leaf = int(np.bincount(geo.leaf).argmax())
+        idx = np.flatnonzero(geo.leaf == leaf)
+        locs[idx[1:21]] = locs[idx[0]]
+        geo = Geometry(locs, 2, 3, 4, 16)
+        bad = np.array([0.0, math.log(0.1), -200.0])
+        where = (3, leaf)
+    print("breakdown case %s" % case, flush=True)
+    with pytest.raises(LinAlgError):
+        mra.loglik(geo, z, "matern32", bad)
+    ths = np.stack([_th(1, 0.1, 0.01), bad, _th(2, 0.2, 0.02)])
+    for flags in (MRA_SYNC, MRA_SYNC | MRA_PLAIN):
+        p = Plan(locs, M=3, J=4, r=16, cov="matern32", max_theta=3, flags=flags)
+        with pytest.raises(MRAError) as e:
+            p.loglik_grad(z, ths)
+        assert e.value.status == _lib.MRA_ENOTPD
+        assert _last_failure(p) == (1, where[0], where[1])
+    q = Plan(locs, M=3, J=4, r=16, cov="matern32", max_theta=3, flags=0)
+    ll, gr = q.loglik_grad(z, ths)
+    ll, gr = ll.cpu().numpy(), gr.cpu().numpy()
+    assert math.isnan(ll[1]) and np.isnan(gr[1]).all()
+    for i in (0, 2):
+        ref = _oracle(locs, z, "matern32", ths[i], 3, 4, 16)
+        assert abs(ll[i] - ref) <= RTOL * abs(ref)
+
+
 def test_no_grad_plan_matches_and_refuses_gradient():
     from paper_1507_04789_amd import MRA_NO_GRAD
     w = wl.clustered(n=32768, M=4, r=64)
