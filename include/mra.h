@@ -87,7 +87,7 @@ typedef enum { MRA_COV_EXPONENTIAL = 0, MRA_COV_MATERN32 = 1 } mra_cov;
 typedef struct {
   int32_t d;            /* spatial dimension: 1 or 2 */
   int32_t M;            /* number of partition levels; M = 0 is the exact GP (Sec. 2.4) */
-  int32_t J;            /* children per region: d = 2: 1 or 4 (quadrants); d = 1: 1..8 */
+  int32_t J;            /* children per region: d = 2: 1, 2, 4, 8 or 16; d = 1: 1..16 */
   int32_t r;            /* knots per region below level M, 1..64; d = 2 default knots need a square r */
   double lo[2], hi[2];  /* domain box (only the first d entries are read) */
   int32_t cov;          /* mra_cov */

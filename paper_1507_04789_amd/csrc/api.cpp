@@ -1,6 +1,7 @@
 // C ABI of the M-RA library (declared in include/mra.h).
 #include <hip/hip_runtime.h>
 
+#include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -216,24 +217,37 @@ mra_status copy_out(const std::string& j, char* out, size_t cap, size_t* len) {
   return MRA_OK;
 }
 
-// value of "key": in a flat JSON text: a quoted string or a number
-bool json_value(const char* js, const char* key, std::string& val) {
+// value of "key": in a flat JSON text, a quoted string or a number:
+// 1 found, 0 key absent, -1 key present with a malformed value
+int json_value(const char* js, const char* key, std::string& val) {
   const std::string k = std::string("\"") + key + "\"";
   const char* p = std::strstr(js, k.c_str());
-  if (!p) return false;
+  if (!p) return 0;
   p += k.size();
   while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
-  if (*p != ':') return false;
+  if (*p != ':') return -1;
   ++p;
   while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
   val.clear();
   if (*p == '"') {
     ++p;
     while (*p && *p != '"') val += *p++;
-    return *p == '"';
+    return *p == '"' ? 1 : -1;
   }
   while (*p && (*p == '-' || (*p >= '0' && *p <= '9'))) val += *p++;
-  return !val.empty();
+  return val.empty() ? -1 : 1;
+}
+
+// a JSON number token that is a whole integer in [lo, hi]; anything else
+// ("--3", "1-2", out-of-range digits) is refused rather than wrapped
+bool parse_int(const std::string& v, int lo, int hi, int32_t& out) {
+  if (v.empty() || v.size() > 12) return false;
+  char* end = nullptr;
+  errno = 0;
+  const long long x = std::strtoll(v.c_str(), &end, 10);
+  if (errno != 0 || end != v.c_str() + v.size() || x < lo || x > hi) return false;
+  out = (int32_t)x;
+  return true;
 }
 
 mra_status check_call(const mra_plan_s* H, int nth) {
@@ -472,8 +486,6 @@ mra_status mra_gls(mra_plan_t P, const double* d_y, const double* d_X, int32_t p
   hipStream_t st = (hipStream_t)stream;
   set_call_work(P);
   P->last_nth = 1;
-  const bool prof = P->prof && P->prof->enabled;
-  (void)prof;
   s = check_hip(launch_gls(*P, d_y, d_X, p, d_theta, d_beta, d_loglik, d_XtSiX, d_grad, d_resid, st));
   if (s != MRA_OK) return s;
   if (P->cfg.flags & MRA_SYNC) return collect_failures(P, 1, st);
@@ -565,22 +577,20 @@ mra_status mra_set_tuning(mra_plan_t P, const char* json) {
   int32_t big = P->big_tiles;
   std::string v;
   for (int f = 0; f < F_COUNT; ++f) {
-    if (!json_value(json, fam_name(f), v)) continue;
+    const int got = json_value(json, fam_name(f), v);
+    if (got < 0) return MRA_EINVAL;
+    if (got == 0) continue;
     int m = -1;
     for (int c = 0; c < 4; ++c)
       if (v == map_name(c)) m = c;
     if (m < 0) return MRA_EINVAL;
     t[f] = (uint8_t)m;
   }
-  if (json_value(json, "big_leaf_tiles", v)) {
-    big = std::atoi(v.c_str());
-    if (big < 0 || big > 64) return MRA_EINVAL;
-  }
+  int got = json_value(json, "big_leaf_tiles", v);
+  if (got < 0 || (got > 0 && !parse_int(v, 0, 64, big))) return MRA_EINVAL;
   int32_t sides = P->side_solves;
-  if (json_value(json, "side_solves", v)) {
-    sides = std::atoi(v.c_str());
-    if (sides < 0 || sides > 64) return MRA_EINVAL;
-  }
+  got = json_value(json, "side_solves", v);
+  if (got < 0 || (got > 0 && !parse_int(v, 0, 64, sides))) return MRA_EINVAL;
   std::memcpy(P->tune, t, sizeof t);
   P->big_tiles = big;
   P->side_solves = sides;

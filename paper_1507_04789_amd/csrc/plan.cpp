@@ -27,11 +27,16 @@ struct Box {
   double a[2], b[2];
 };
 
-// split of one region into g_x x g_y children
+// split of one region into g_x x g_y children: the g_y - 1 y split values,
+// then for each slab its g_x - 1 x split values (at most 15 in all: 4 x 4 in
+// 2-D, 16 x 1 in 1-D)
 struct Split {
   int gx = 1, gy = 1;
-  double ys[3] = {};      // g_y - 1 y split values
-  double xs[4][3] = {};   // per slab: g_x - 1 x split values
+  double v[15] = {};
+  const double* ys() const { return v; }
+  double* ys() { return v; }
+  const double* xs(int iy) const { return v + (gy - 1) + iy * (gx - 1); }
+  double* xs(int iy) { return v + (gy - 1) + iy * (gx - 1); }
 };
 
 bool grid_shape(int d, int J, const Box& box, int& gx, int& gy) {
@@ -71,9 +76,9 @@ int child_index(const Split& s, const double* x, int d) {
   int iy = 0, ix = 0;
   if (d == 2)
     for (int k = 0; k < s.gy - 1; ++k)
-      if (x[1] >= s.ys[k]) ++iy;
+      if (x[1] >= s.ys()[k]) ++iy;
   for (int k = 0; k < s.gx - 1; ++k)
-    if (x[0] >= s.xs[iy][k]) ++ix;
+    if (x[0] >= s.xs(iy)[k]) ++ix;
   return iy * s.gx + ix;
 }
 
@@ -81,11 +86,11 @@ Box child_box(const Box& p, const Split& s, int j, int d) {
   Box c = p;
   const int iy = j / s.gx, ix = j % s.gx;
   if (d == 2) {
-    c.a[1] = iy == 0 ? p.a[1] : s.ys[iy - 1];
-    c.b[1] = iy == s.gy - 1 ? p.b[1] : s.ys[iy];
+    c.a[1] = iy == 0 ? p.a[1] : s.ys()[iy - 1];
+    c.b[1] = iy == s.gy - 1 ? p.b[1] : s.ys()[iy];
   }
-  c.a[0] = ix == 0 ? p.a[0] : s.xs[iy][ix - 1];
-  c.b[0] = ix == s.gx - 1 ? p.b[0] : s.xs[iy][ix];
+  c.a[0] = ix == 0 ? p.a[0] : s.xs(iy)[ix - 1];
+  c.b[0] = ix == s.gx - 1 ? p.b[0] : s.xs(iy)[ix];
   return c;
 }
 
@@ -198,7 +203,7 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
       if (d == 2) {
         vy.clear();
         for (int64_t q = p0; q < p1; ++q) vy.push_back(h_locs[byreg[q] * d + 1]);
-        split_values(bx.a[1], bx.b[1], sp.gy, d, adaptive ? &vy : nullptr, sp.ys);
+        split_values(bx.a[1], bx.b[1], sp.gy, d, adaptive ? &vy : nullptr, sp.ys());
       }
       for (int iy = 0; iy < sp.gy; ++iy) {
         vx.clear();
@@ -207,10 +212,10 @@ mra_status build_plan(const mra_config* cfg, const double* h_locs, int64_t n, co
           int cy = 0;
           if (d == 2)
             for (int k = 0; k < sp.gy - 1; ++k)
-              if (x[1] >= sp.ys[k]) ++cy;
+              if (x[1] >= sp.ys()[k]) ++cy;
           if (cy == iy) vx.push_back(x[0]);
         }
-        split_values(bx.a[0], bx.b[0], sp.gx, d, adaptive ? &vx : nullptr, sp.xs[iy]);
+        split_values(bx.a[0], bx.b[0], sp.gx, d, adaptive ? &vx : nullptr, sp.xs(iy));
       }
       for (int j = 0; j < J1; ++j) boxes[m + 1][i * J1 + j] = child_box(bx, sp, j, d);
     }

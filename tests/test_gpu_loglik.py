@@ -181,6 +181,35 @@ def test_breakdown_matches_oracle(case):
         assert abs(ll[i] - ref) <= RTOL * abs(ref)
 
 
+def test_knots_equal_to_ancestor_knots_break_down():
+    """Eight knots of level-1 region 2 placed on root knots: that region's
+    prior K^{-1} is singular for every parameter vector (its rows for those
+    knots vanish once the root is conditioned on).  The oracle raises
+    LinAlgError; the library names row 0, level 1, region 2, and without
+    MRA_SYNC every row reads NaN."""
+    from numpy.linalg import LinAlgError
+    from paper_1507_04789_amd import _lib
+    g = np.random.default_rng(90)
+    locs = g.random((800, 2))
+    z = g.standard_normal(800)
+    kn = [np.array(k, copy=True) for k in Geometry(locs, 2, 3, 4, 16).knots]
+    kn[1][2][:8] = kn[0][0][8:16]
+    geo = Geometry(locs, 2, 3, 4, 16, knots=kn)
+    ths = np.stack([_th(1, 0.1, 0.01), _th(2, 0.2, 0.02), _th(1, 0.3, 0.05)])
+    for th in ths:
+        with pytest.raises(LinAlgError):
+            mra.loglik(geo, z, "matern32", th)
+    print("breakdown case: knots on ancestor knots", flush=True)
+    p = Plan(locs, M=3, J=4, r=16, cov="matern32", knots=kn, max_theta=3, flags=MRA_SYNC)
+    with pytest.raises(MRAError) as e:
+        p.loglik_grad(z, ths)
+    assert e.value.status == _lib.MRA_ENOTPD
+    assert _last_failure(p) == (0, 1, 2)
+    q = Plan(locs, M=3, J=4, r=16, cov="matern32", knots=kn, max_theta=3, flags=0)
+    ll, gr = q.loglik_grad(z, ths)
+    assert torch.isnan(ll).all() and torch.isnan(gr).all()
+
+
 def test_no_grad_plan_matches_and_refuses_gradient():
     from paper_1507_04789_amd import MRA_NO_GRAD
     w = wl.clustered(n=32768, M=4, r=64)
