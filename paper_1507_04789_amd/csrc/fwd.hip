@@ -135,8 +135,10 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
 }
 
 // Y = L_Sigma^{-1} X for one column plane of one leaf (forward substitution
-// by tiles with the inverted diagonal tiles)
-__global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
+// by tiles with the inverted diagonal tiles).  The data plane M holds zc
+// nonzero columns (a multiple of 16: z and the trend columns); the others
+// stay zero and are not multiplied.
+__global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, int zc, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -151,6 +153,7 @@ __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
   const double* X = S + P.off_wobs + cpl * P.plane + poff * T;
   double* Y = S + P.off_y + cpl * P.plane + poff * T;
   const int nR = P.leaf_n[leaf];
+  const int nc = cpl == P.M ? zc : T;
   Acc acc;
   for (int ib = 0; ib < nb; ++ib) {
     const int mr = round16(min(T, nR - T * ib));
@@ -159,13 +162,13 @@ __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, TaskMap tm) {
       acc_load(acc, R, T);
       gemm_segs2(acc, ib,
                 [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
-                lds, mr);
+                lds, mr, nc);
       acc_store(acc, Y + (int64_t)ib * TT, T);
       __syncthreads();
       R = Y + (int64_t)ib * TT;
     }
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr, nc);
     acc_store(acc, Y + (int64_t)ib * TT, T);
     __syncthreads();
   }
@@ -393,6 +396,10 @@ DevPlan chunk_plan(const mra_plan_s& H, int c) {
   return P;
 }
 
+// nonzero columns of the data plane, rounded up to the 16-column MFMA block:
+// z and px trend columns
+static int zcols(int px) { return (px + 1 + 15) / 16 * 16; }
+
 // share of a whole-plan flop count carried by the tasks [a, b) of n
 static double share(double f, int64_t a, int64_t b, int64_t n) { return n > 0 ? f * (double)(b - a) / (double)n : 0.0; }
 
@@ -431,7 +438,7 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
   }
   run.tuned(F_TRSM, MAP_GROUPED, factor ? "leaf_trsm" : "leaf_trsm_re", -1,
             factor ? H.trsm_flops_big(f1) - H.trsm_flops_big(f0) : 0.0, M + 1, nullptr, k_leaf_trsm, f0 * (M + 1),
-            f1 * (M + 1));
+            f1 * (M + 1), zcols(px));
   (void)nfac;
   return hipGetLastError();
 }
@@ -481,13 +488,13 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
     Runner rs{P, nth, side->s, false, H.prof, H.tune};
     const double fpb = H.potrf_flops_big(nbig), ftb = H.trsm_flops_big(nbig);
     rs.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf_big", -1, fpb, 1, nullptr, k_leaf_potrf, 0, nbig);
-    rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm, 0, nbig * (M + 1));
+    rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm, 0, nbig * (M + 1), zcols(px));
     if ((e = hipEventRecord(side->big, side->s)) != hipSuccess) return e;
   }
   run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, F.potrf - H.potrf_flops_big(nbig), 1, nullptr, k_leaf_potrf, nbig,
             nfac);
   run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm,
-            nbig * (M + 1), ntrsm);
+            nbig * (M + 1), ntrsm, zcols(px));
   return hipGetLastError();
 }
 

@@ -155,6 +155,9 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   const double* Y = S + P.off_y + cpl * P.plane + poff * T;
   double* V = S + P.off_v + cpl * P.plane + poff * T;
   const int nR = P.leaf_n[leaf];
+  // the reverse pass reads only column 0 of the data plane's V (the data
+  // plane's other columns are zero or, after a trend fit, cleared)
+  const int nc = cpl == P.M ? 16 : T;
   Acc acc;
   for (int ib = nb - 1; ib >= 0; --ib) {
     const int mr = round16(min(T, nR - T * ib));
@@ -164,13 +167,13 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
       gemm_segs2(acc, nb - 1 - ib, [&](int q) {
         const int jb = ib + 1 + q;
         return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
-      }, lds, mr);
+      }, lds, mr, nc);
       acc_store(acc, V + (int64_t)ib * TT, T);
       __syncthreads();
       R = V + (int64_t)ib * TT;
     }
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr);
+    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr, nc);
     acc_store(acc, V + (int64_t)ib * TT, T);
     __syncthreads();
   }
@@ -292,8 +295,10 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
   Acc acc;
   acc_zero(acc);
   gemm_segs2(acc, P.M + 1 + (nb - bi), [&](int q) {
+    // Q of the data plane is zero outside column 0: K = 16 covers it
     if (q <= P.M)
-      return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0);
+      return seg<Op::N, Op::T>(S + P.off_q + q * P.plane + pi * T, T, S + P.off_v + q * P.plane + pj * T, T, -1.0,
+                               q == P.M ? 1 : T / KC);
     const int kb = bi + q - (P.M + 1);
     return seg<Op::T, Op::N>(li(kb, bi), T, li(kb, bj), T, -0.5);
   }, lds, round16(nvi), round16(nvj));
