@@ -107,8 +107,9 @@ def _src_digest() -> str:
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         # the kernels, their headers and the plan (task lists); not the ABI
-        # glue (api.cpp) or the scratch array of the no-allocation call
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")) and f not in ("api.cpp", "noalloc.hip"):
+        # glue (api.cpp), the scratch array of the no-allocation call or the
+        # stand-alone engine probe
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")) and f not in ("api.cpp", "noalloc.hip", "engine_probe.hip"):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
@@ -261,6 +262,58 @@ def summarize_profiles(root: str, copy_bytes: int):
         out.append("machine-readable (kernel, executed FP64 MFMA flops per launch, MFMA busy %, source digest):")
         for name, nd, e, tf, u in mrows:
             out.append("mfma %s %.6g %.4g src %s" % (name, e, u, _src_digest()))
+    out += _timeline(find("trace", "kernel_trace.csv"))
+    print("\n".join(out))
+
+
+def _timeline(path: str, step: int = 2):
+    """Launch timeline of one step of the traced run: every kernel's start
+    and end relative to the step's first launch, with its hardware queue.
+    Step 2 of a `--steps 3 --warmup 1` run is the second timed graph replay
+    (step 0 is the warm-up, steps 4..6 the eager profiled pass)."""
+    rows = [r for r in _csv(path) if r["Kernel_Name"].startswith("mra::")]
+    starts = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "init"]
+    if len(starts) <= step:
+        return []
+    a = starts[step]
+    b = starts[step + 1] if step + 1 < len(starts) else len(rows)
+    st = rows[a:b]
+    t0 = min(int(r["Start_Timestamp"]) for r in st)
+    t1 = max(int(r["End_Timestamp"]) for r in st)
+    out = ["", "timeline of step %d of the traced run (a timed graph replay): %.3f ms from first start to last end"
+           % (step, (t1 - t0) / 1e6),
+           "%-16s %5s %10s %10s %9s %9s" % ("kernel", "queue", "start_us", "end_us", "dur_us", "blocks")]
+    for r in sorted(st, key=lambda r: int(r["Start_Timestamp"])):
+        s0 = (int(r["Start_Timestamp"]) - t0) / 1e3
+        s1 = (int(r["End_Timestamp"]) - t0) / 1e3
+        out.append("%-16s %5s %10.1f %10.1f %9.1f %9d" % (_short(r["Kernel_Name"]), r["Queue_Id"], s0, s1, s1 - s0,
+                                                        int(r["Grid_Size_X"]) // 256))
+    return out
+
+
+def summarize_engine(root: str):
+    """Text summary of the tile-engine probe run: root/engine.log (the
+    probe's own HIP-event timings) and root/engine (rocprofv3 kernel stats of
+    the same run)."""
+    out = ["command:",
+           "  rocprofv3 --kernel-trace --stats --output-format csv -d %s/engine -o run -- "
+           "./paper_1507_04789_amd/engine_probe" % root,
+           "",
+           "probe output (HIP events over 10 launches after a warm-up; FP64 TFLOP/s of the tile products):"]
+    for line in open(os.path.join(root, "engine.log")):
+        if re.match(r"^(library|A row|A k)", line):
+            out.append("  " + line.rstrip())
+    stats = None
+    for dp, _, fs in os.walk(os.path.join(root, "engine")):
+        for f in fs:
+            if f.endswith("kernel_stats.csv"):
+                stats = _csv(os.path.join(dp, f))
+    if stats:
+        out += ["", "rocprofv3 --stats (all launches of each kernel, both segment counts):",
+                "%-40s %6s %12s" % ("kernel", "calls", "avg_us")]
+        for r in stats:
+            name = re.sub(r"\(anonymous namespace\)::|\(double const\*.*$", "", r["Name"]).replace("void ", "")
+            out.append("%-40s %6s %12.1f" % (name[:40], r["Calls"], float(r["AverageNs"]) / 1e3))
     print("\n".join(out))
 
 
@@ -438,9 +491,14 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="print the text summary of a profiling directory and exit")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--summarize-engine", metavar="DIR",
+                    help="print the text summary of a tile-engine probe run (DIR/engine.log, DIR/engine) and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.copy_bytes)
+        return
+    if args.summarize_engine:
+        summarize_engine(args.summarize_engine)
         return
     if args.copy_probe:
         copy_probe(args.copy_probe)

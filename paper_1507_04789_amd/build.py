@@ -36,10 +36,27 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE = os.path.join(HERE, "engine_probe")
+
+
+def build_probe() -> str:
+    """The tile engine's throughput probe (csrc/engine_probe.hip), a
+    stand-alone measurement program beside the library."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", os.path.join(CSRC, "engine_probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    shutil.move(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        probe = ex.submit(build_probe)
         objs = list(ex.map(_compile, SOURCES))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
