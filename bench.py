@@ -352,7 +352,8 @@ def secondary_configs(dev, w2, theta_batch):
     the clustered n = 2^18 log-likelihood alone, and 64 parameter vectors on
     the clustered data (log kappa ~ U[log 0.02, log 0.3], log sigma^2 ~
     U[-1, 1], log tau^2 ~ U[-6, -2], seed 41) in batches of theta_batch
-    vectors per call (one launch per level for the whole batch)."""
+    vectors per call (one launch per level for the whole batch), the GLS
+    trend call, and the clustered data partitioned by quantile splits."""
     import torch
     from paper_1507_04789_amd import MRA_GRAPH, MRA_NO_GRAD, Plan
     from paper_1507_04789_amd import workloads as wl
@@ -414,6 +415,19 @@ def secondary_configs(dev, w2, theta_batch):
         "fp64_pct_peak": 100.0 * 64 * p4.info["flops_grad"] / (ms4 * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
         "finite": bool(torch.isfinite(lls).all())}
     del p4
+    torch.cuda.empty_cache()
+    # the same clustered data with data-adaptive (quantile) splits: equal
+    # leaf counts instead of the quadrants' 0..542, so less padding and no
+    # large leaves; its own algorithmic flop count
+    pa = Plan(w2.locs, M=w2.M, J=w2.J, r=w2.r, cov=w2.cov, adaptive=True, flags=MRA_GRAPH)
+    pa.bind(dev)
+    oa = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty(1, 3, dtype=torch.float64, device=dev))
+    ms_a = _time_calls(lambda: pa.loglik_grad(z2, t2, out=oa), 10)
+    res["clustered_n262144_adaptive_splits_loglik_grad"] = {
+        "ms": ms_a, "evals_per_s": 1000.0 / ms_a, "max_leaf": int(pa.info["max_leaf"]),
+        "fp64_pct_peak": 100.0 * pa.info["flops_grad"] / (ms_a * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
+        "loglik": float(oa[0][0])}
+    del pa
     torch.cuda.empty_cache()
     return res
 
