@@ -410,10 +410,11 @@ def secondary_configs(dev, w2, theta_batch):
             p4.loglik_grad(z2, c, out=o)
     ms4 = _time_calls(all64, 2, warmup=1)
     lls = torch.cat([o[0] for o in outs])
+    grads = torch.cat([o[1] for o in outs])
     res["clustered_n262144_64theta_loglik_grad"] = {
         "ms_for_64": ms4, "evals_per_s": 64 * 1000.0 / ms4, "theta_per_call": B,
         "fp64_pct_peak": 100.0 * 64 * p4.info["flops_grad"] / (ms4 * 1e-3) / (PEAK_FP64_TFLOPS * 1e12),
-        "finite": bool(torch.isfinite(lls).all())}
+        "finite": bool(torch.isfinite(lls).all() and torch.isfinite(grads).all())}
     del p4
     torch.cuda.empty_cache()
     # the same clustered data with data-adaptive (quantile) splits: equal
