@@ -138,7 +138,7 @@ def test_autograd_per_row_data():
     for b in range(3):
         _check(yv.grad[b].cpu().numpy(), wts[b] * predict.data_gradient(geo, Y[b], "matern32", ths[b]))
         rll, rg, _ = mra.loglik(geo, Y[b], "matern32", ths[b], grad=True)
-        assert abs(float(ll[b]) - rll) <= 1e-10 * abs(rll)
+        assert abs(float(ll[b].detach()) - rll) <= 1e-10 * abs(rll)
         gt = tv.grad[b].cpu().numpy()
         assert (np.abs(gt - wts[b] * rg) <= 1e-6 * np.abs(wts[b] * rg)).all(), (gt, wts[b] * rg)
 
