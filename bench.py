@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PROFILE_SUMMARY = "clustered_n262144_loglik_grad_counters.txt"
 METRIC = "M-RA loglik+grad evals/s at n=2^18 (batched vs plain, 1 GPU); FP64 MFMA % peak"
 
@@ -315,6 +316,16 @@ def summarize_engine(root: str):
             name = re.sub(r"\(anonymous namespace\)::|\(double const\*.*$", "", r["Name"]).replace("void ", "")
             out.append("%-40s %6s %12.1f" % (name[:40], r["Calls"], float(r["AverageNs"]) / 1e3))
     print("\n".join(out))
+
+
+def _hbm_side(traffic, avg_ms: float):
+    """The dominant kernel against the HBM roof as well: its measured L2-miss
+    traffic per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; this also
+    counts reads served by the Infinity Cache) over its mean launch time."""
+    if traffic is None or avg_ms <= 0:
+        return None
+    gbps = traffic / (avg_ms * 1e-3) / 1e9
+    return {"achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": gbps / PEAK_HBM_GBPS}
 
 
 def _executed(kernel: str, alg_flops: float, avg_ms: float):
@@ -652,7 +663,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": _stored_traffic(dom["name"]), "traffic_unit": "bytes",
                      "flops_per_launch": per_launch_flops, "avg_launch_ms": avg_ms,
-                     "executed": _executed(dom["name"], per_launch_flops, avg_ms)},
+                     "executed": _executed(dom["name"], per_launch_flops, avg_ms),
+                     "hbm": _hbm_side(_stored_traffic(dom["name"]), avg_ms)},
         "kernels": [{"name": f["name"], "ms_per_step": f["total_ms"] / prof_steps,
                      "tflops": (f["flops"] / (f["total_ms"] * 1e-3) / 1e12) if f["total_ms"] > 0 else None}
                     for f in fam],
