@@ -243,6 +243,28 @@ def test_gls_small_against_oracle(M, r, n):
         np.testing.assert_allclose(out["resid"], z - X @ rb, rtol=0, atol=1e-9 * np.abs(z).max())
 
 
+@pytest.mark.parametrize("p", [20, 63])
+def test_gls_many_trend_columns(p):
+    """Trend columns beyond the first 16-column block of the data plane (the
+    solves multiply round16(1 + p) columns), up to the limit p = 63, stored
+    and checkpointed, against the oracle's GLS."""
+    g = np.random.default_rng(61 + p)
+    n = 1500
+    locs = g.random((n, 2))
+    X = np.concatenate([np.ones((n, 1)), g.standard_normal((n, p - 1))], axis=1)
+    z = g.standard_normal(n) + X @ (0.3 * g.standard_normal(p))
+    th = _th(0.9, 0.15, 0.03)
+    print("gls case n=%d p=%d" % (n, p), flush=True)
+    rb, rll, rg, rA = predict.gls(Geometry(locs, 2, 2, 4, 9), z, X, "matern32", th)
+    for flags in (MRA_SYNC, MRA_SYNC | MRA_CHECKPOINT):
+        q = Plan(locs, M=2, J=4, r=9, cov="matern32", flags=flags, chunks=3)
+        out = {k: v.cpu().numpy() for k, v in q.gls(z, X, th).items()}
+        np.testing.assert_allclose(out["beta"], rb, rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(out["XtSiX"], rA, rtol=1e-9, atol=1e-12 * np.abs(rA).max())
+        assert abs(out["loglik"][0] - rll) <= 1e-10 * abs(rll)
+        assert (np.abs(out["grad"] - rg) <= 1e-6 * np.abs(rg) + 1e-9 * np.abs(rg).max()).all(), (out["grad"], rg)
+
+
 def test_gls_full_size_normal_equations():
     """n = 2^18 clustered workload plus the trend 0.5 + x - y: the residual
     of the GLS fit satisfies the normal equations X' Sigma^{-1} r = 0 (checked
