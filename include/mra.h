@@ -121,7 +121,7 @@ typedef struct {
   double flops_grad;    /* algorithmic FP64 flops of one log-likelihood + gradient */
   double flops_predict; /* algorithmic FP64 flops of one prediction pass */
   int64_t n_sim_normals; /* standard normals per draw of mra_simulate: 64 per region below
-                            level M (sum_{m<M} J^m regions, the first r used) + n_pred */
+                            level M (the first r_m used) + n_pred */
 } mra_info;
 
 /*
@@ -278,9 +278,10 @@ mra_status mra_predict(mra_plan_t plan, const double* d_y, const double* d_theta
  * the prediction locations, d_out[n_draws][n_pred], from caller-supplied
  * standard normals d_eps[n_draws][eps_stride], eps_stride >= n_sim_normals
  * of mra_get_info: row d holds 64 normals per region below level M in
- * level-major, region-major order ((sum_{l<m} J^l + i) * 64 for region
- * (m, i), of which the first r are used) followed by one normal per
- * prediction location in the caller's order.  Draw d is
+ * level-major, region-major order ((N_m + i) * 64 for region (m, i), N_m
+ * the number of regions above level m, i.e. sum_{l<m} J_1 ... J_l; the
+ * first r_m of the 64 are used) followed by one normal per prediction
+ * location in the caller's order.  Draw d is
  *   mean + sum_m B~^{m+1,m} Lt_{a_m}^{-T} xi_{a_m} + chol(remainder block) xi_R
  * (Lt Lt' the whitened K~^{-1}), a linear function of the normals.  The
  * prediction locations of a leaf must be distinct (the remainder block is

@@ -62,6 +62,26 @@ def test_predict_cov_against_oracle(case, ckpt):
     assert (np.abs(v2.cpu().numpy() - np.diag(C)) <= 1e-12 * math.exp(th[0])).all()
 
 
+@pytest.mark.parametrize("adaptive", [False, True], ids=["equal", "quantile"])
+def test_predict_cov_mixed_levels(adaptive):
+    """Level-dependent J_m = (2, 8, 4) and r_m = (16, 9, 4), with equal-area
+    or quantile splits: the regions shared by two prediction points follow
+    the per-level child counts."""
+    w = wl.clustered(n=6000, M=3)
+    pred = np.random.default_rng(71).random((350, 2))
+    th = _th(1.1, 0.12, 0.02)
+    Jl, rl = (2, 8, 4), (16, 9, 4)
+    print("joint mixed-level case n=6000 n_pred=350 adaptive=%s" % adaptive, flush=True)
+    p = Plan(w.locs, M=3, J=4, r=4, cov="matern32", pred=pred, flags=MRA_SYNC | MRA_JOINT, J_levels=Jl,
+             r_levels=rl, adaptive=adaptive)
+    mu, C = p.predict_cov(w.z, th)
+    mu, C = mu.cpu().numpy(), C.cpu().numpy()
+    geo = Geometry(w.locs, 2, 3, 4, 4, J_levels=Jl, r_levels=rl, adaptive=adaptive)
+    rmu, rC = predict.predict_joint(geo, w.z, "matern32", th, pred)
+    assert (np.abs(mu - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
+    _cmp_cov(C, rC, math.exp(th[0]))
+
+
 def test_predict_cov_swath_pruned_and_empty_leaves():
     # most regions hold no observation (pruned posterior), prediction points
     # in the gaps (prior-only regions) and in leaves without observations
@@ -100,6 +120,32 @@ def test_simulate_factor_reproduces_covariance():
         cols.append(p.simulate(z, th, eps).cpu().numpy() - mean[None, :])
     F = np.concatenate(cols, axis=0).T          # (n_pred, ne)
     rmu, rC = predict.predict_joint(Geometry(locs, 2, 2, 4, 9), z, "matern32", th, pred)
+    assert (np.abs(mean - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
+    _cmp_cov(F @ F.T, rC, math.exp(th[0]))
+
+
+def test_simulate_factor_mixed_levels():
+    """As above with J_m = (2, 8) and r_m = (9, 16): the normals of region
+    (m, i) sit at (N_m + i) * 64, N_m the regions above level m."""
+    g = np.random.default_rng(73)
+    locs, z = g.random((1500, 2)), g.standard_normal(1500)
+    pred = g.random((150, 2))
+    th = _th(0.9, 0.1, 0.03)
+    print("simulate factor mixed-level case n=1500 n_pred=150 J=(2,8) r=(9,16)", flush=True)
+    p = Plan(locs, M=2, J=4, r=4, cov="matern32", pred=pred, flags=MRA_SYNC | MRA_JOINT, J_levels=(2, 8),
+             r_levels=(9, 16))
+    ne = int(p.info["n_sim_normals"])
+    assert ne == (1 + 2) * 64 + 150
+    mean = p.simulate(z, th, np.zeros((1, ne)))[0].cpu().numpy()
+    cols = []
+    for k0 in range(0, ne, 64):
+        k1 = min(ne, k0 + 64)
+        eps = np.zeros((k1 - k0, ne))
+        eps[np.arange(k1 - k0), np.arange(k0, k1)] = 1.0
+        cols.append(p.simulate(z, th, eps).cpu().numpy() - mean[None, :])
+    F = np.concatenate(cols, axis=0).T
+    geo = Geometry(locs, 2, 2, 4, 4, J_levels=(2, 8), r_levels=(9, 16))
+    rmu, rC = predict.predict_joint(geo, z, "matern32", th, pred)
     assert (np.abs(mean - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
     _cmp_cov(F @ F.T, rC, math.exp(th[0]))
 
