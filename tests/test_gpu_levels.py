@@ -1,8 +1,8 @@
 """Level-dependent J_m, r_m and data-adaptive splits on the GPU against the
-oracle: log-likelihood (1e-10 relative), gradient (1e-6 per component) and
-kriging (1e-10 entry by entry), with 2-D splits into 2, 4, 8 and 16
-children, knot counts from 1 to 64 per level, quantile splits of clustered
-data, and one dimension; plus the satellite application's J_m =
+oracle: log-likelihood (1e-10 relative), gradient (1e-6 per component),
+data gradient and GLS trend, and kriging (1e-10 entry by entry), with 2-D
+splits into 2, 4, 8 and 16 children, knot counts from 1 to 64 per level,
+quantile splits of clustered data, and one dimension; plus the satellite application's J_m =
 (2, 2, 4, 8, 8, 16) at n = 2^18 with the properties that hold at any size
 (the scale identity and central differences)."""
 import math
@@ -52,16 +52,26 @@ def test_levels_against_oracle(case):
     geo = Geometry(locs, d, M, 4, 4, J_levels=Jl, r_levels=rl, adaptive=adaptive)
     rll, rg, _ = mra.loglik(geo, z, kind, th, grad=True)
     rmu, rvar = predict.predict(geo, z, kind, th, pred)
+    rgy = predict.data_gradient(geo, z, kind, th)
+    X = np.concatenate([np.ones((n, 1)), locs], axis=1)          # trend 1, x (, y)
+    zt = z + X @ np.linspace(0.5, -1.0, X.shape[1])
+    rb, rlt, rgt, _ = predict.gls(geo, zt, X, kind, th)
     for flags in (MRA_SYNC, MRA_SYNC | MRA_CHECKPOINT):
         p = Plan(locs, M=M, J=4, r=4, d=d, cov=kind, J_levels=Jl, r_levels=rl, adaptive=adaptive, pred=pred,
                  flags=flags, chunks=2)
-        ll, gr = p.loglik_grad(z, th)
+        ll, gr, gy = p.loglik_grad_data(z, th)
         mu, var = p.predict(z, th)
-        ll, gr, mu, var = float(ll[0]), gr[0].cpu().numpy(), mu.cpu().numpy(), var.cpu().numpy()
+        ll, gr, gy = float(ll[0]), gr[0].cpu().numpy(), gy[0].cpu().numpy()
+        mu, var = mu.cpu().numpy(), var.cpu().numpy()
         assert abs(ll - rll) <= 1e-10 * abs(rll), (ll, rll)
         assert (np.abs(gr - rg) <= 1e-6 * np.abs(rg)).all(), (gr, rg)
+        assert (np.abs(gy - rgy) <= 1e-6 * np.abs(rgy) + 1e-9 * np.abs(rgy).max()).all()
         assert (np.abs(mu - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
         assert (np.abs(var - rvar) <= 1e-10 * rvar + 1e-12 * math.exp(th[0])).all()
+        out = {k: v.cpu().numpy() for k, v in p.gls(zt, X, th).items()}
+        np.testing.assert_allclose(out["beta"], rb, rtol=1e-8, atol=1e-10)
+        assert abs(out["loglik"][0] - rlt) <= 1e-10 * abs(rlt)
+        assert (np.abs(out["grad"] - rgt) <= 1e-6 * np.abs(rgt) + 1e-9 * np.abs(rgt).max()).all()
 
 
 def test_satellite_levels_full_size_properties():
