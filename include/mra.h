@@ -325,8 +325,11 @@ mra_status mra_last_failure(mra_plan_t plan, int32_t* theta_idx, int32_t* level,
  * if cap is too small, the table is applied anyway).  d_loglik [n_theta] and
  * d_grad [n_theta][3] are scratch outputs.  Synchronises `stream`.
  * mra_get_tuning writes the current table; mra_set_tuning applies a table
- * produced by either (unknown keys are ignored, unknown shapes give
- * MRA_EINVAL).  Both drop captured graphs.  Host only apart from
+ * produced by either: unknown keys are ignored, families the table omits
+ * take their built-in shape, an omitted big_leaf_tiles or side_solves keeps
+ * its value; an unknown shape, a malformed value or an integer outside
+ * 0..64 gives MRA_EINVAL and leaves the table unchanged.  mra_set_tuning
+ * and mra_autotune drop captured graphs.  Host only apart from
  * mra_autotune.
  */
 mra_status mra_autotune(mra_plan_t plan, const double* d_y, const double* d_theta, int32_t n_theta,
