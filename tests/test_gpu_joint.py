@@ -179,3 +179,39 @@ def test_joint_calls_need_the_flag():
     p = Plan(g.random((500, 2)), M=2, J=4, r=9, cov="matern32", pred=g.random((40, 2)))
     with pytest.raises(MRAError):
         p.predict_cov(np.zeros(500), _th(1.0, 0.1, 0.05))
+
+
+def test_bound_plan_argument_checks():
+    """Arguments the library refuses on a bound plan before launching
+    anything: draw counts outside 1..64, a normals stride below
+    n_sim_normals, trend column counts outside 1..63; a valid call on the
+    same plan afterwards still matches the oracle."""
+    from paper_1507_04789_amd import _lib
+    g = np.random.default_rng(74)
+    n, npred = 600, 40
+    locs, z = g.random((n, 2)), g.standard_normal(n)
+    pred = g.random((npred, 2))
+    th = _th(1.0, 0.1, 0.05)
+    p = Plan(locs, M=2, J=4, r=9, cov="matern32", pred=pred, flags=MRA_SYNC | MRA_JOINT)
+    p.bind("cuda:0")
+    L, st = _lib.lib(), p._stream()
+    dev = "cuda:0"
+    zt = torch.tensor(z, device=dev)
+    tt = torch.tensor(th[None], device=dev)
+    ne = int(p.info["n_sim_normals"])
+    eps = torch.zeros(65, ne, dtype=torch.float64, device=dev)
+    out = torch.empty(65, npred, dtype=torch.float64, device=dev)
+    for nd, stride in ((0, ne), (65, ne), (1, ne - 1)):
+        s = L.mra_simulate(p._h, zt.data_ptr(), tt.data_ptr(), eps.data_ptr(), stride, nd, out.data_ptr(), st)
+        assert s == _lib.MRA_EINVAL, (nd, stride, s)
+    X = torch.ones(64, n, dtype=torch.float64, device=dev)
+    beta = torch.empty(64, dtype=torch.float64, device=dev)
+    sc = torch.empty(3 + n + 64 * 64, dtype=torch.float64, device=dev)
+    for pcols in (0, 64):
+        s = L.mra_gls(p._h, zt.data_ptr(), X.data_ptr(), pcols, tt.data_ptr(), beta.data_ptr(), sc.data_ptr(),
+                      sc.data_ptr(), sc.data_ptr(), None, st)
+        assert s == _lib.MRA_EINVAL, (pcols, s)
+    mu, C = p.predict_cov(z, th)
+    rmu, rC = predict.predict_joint(Geometry(locs, 2, 2, 4, 9), z, "matern32", th, pred)
+    assert (np.abs(mu.cpu().numpy() - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
+    _cmp_cov(C.cpu().numpy(), rC, 1.0)
