@@ -424,7 +424,6 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
   const int64_t nrow = (int64_t)H.row_tasks.size() / 2, nsig = (int64_t)H.sig_tasks.size() / 3;
-  const int64_t nfac = (int64_t)H.fac_tasks.size();
   gather_chunk(H, P, c, y, y_stride, nth, st, X, px);
   const int64_t r0 = H.ck_row[c], r1 = H.ck_row[c + 1];
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, factor ? "leaf_rows" : "leaf_rows_re", -1,
@@ -439,7 +438,6 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
   run.tuned(F_TRSM, MAP_GROUPED, factor ? "leaf_trsm" : "leaf_trsm_re", -1,
             factor ? H.trsm_flops_big(f1) - H.trsm_flops_big(f0) : 0.0, M + 1, nullptr, k_leaf_trsm, f0 * (M + 1),
             f1 * (M + 1), zcols(px));
-  (void)nfac;
   return hipGetLastError();
 }
 
