@@ -215,3 +215,27 @@ def test_bound_plan_argument_checks():
     rmu, rC = predict.predict_joint(Geometry(locs, 2, 2, 4, 9), z, "matern32", th, pred)
     assert (np.abs(mu.cpu().numpy() - rmu) <= 1e-10 * np.abs(rmu) + 1e-12 * np.abs(rmu).max()).all()
     _cmp_cov(C.cpu().numpy(), rC, 1.0)
+
+
+def test_plain_form_matches_batched_bitwise():
+    """The one-launch-per-task form (MRA_PLAIN) of the joint covariance, the
+    draws and the GLS trend gives the batched form's bits."""
+    from paper_1507_04789_amd import MRA_PLAIN
+    g = np.random.default_rng(75)
+    n, npred = 900, 60
+    locs, z = g.random((n, 2)), g.standard_normal(n)
+    pred = g.random((npred, 2))
+    th = _th(1.0, 0.12, 0.04)
+    X = np.concatenate([np.ones((n, 1)), locs], axis=1)
+    print("plain vs batched: joint covariance, draws, GLS (n=900, M=2, r=9)", flush=True)
+    outs = []
+    for flags in (MRA_SYNC | MRA_JOINT, MRA_SYNC | MRA_JOINT | MRA_PLAIN):
+        p = Plan(locs, M=2, J=4, r=9, cov="matern32", pred=pred, flags=flags)
+        ne = int(p.info["n_sim_normals"])
+        eps = np.random.default_rng(76).standard_normal((3, ne))
+        mu, C = p.predict_cov(z, th)
+        d = p.simulate(z, th, eps)
+        gl = p.gls(z + X @ np.array([0.5, 1.0, -1.0]), X, th)
+        outs.append([mu.cpu(), C.cpu(), d.cpu()] + [gl[k].cpu() for k in ("beta", "loglik", "grad", "resid")])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
