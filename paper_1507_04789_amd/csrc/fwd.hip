@@ -258,10 +258,12 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
   __shared__ double lds_x[T * PLD];
   __shared__ double red[8];
+  __shared__ double wsh[T];
   const int th = blockIdx.y;
   const int64_t i = P.act_post[P.act_post_off[m] + tk0];
   double* S = slice(P, th);
   Post po = post_of(P, S, m, i);
+  if (threadIdx.x < T) wsh[threadIdx.x] = po.omega(m)[threadIdx.x];
   tile_to_lds(po.A(m, m), T, lds);
   __syncthreads();
   if (threadIdx.x < T) lds[threadIdx.x * PLD + threadIdx.x] += 1.0;
@@ -278,8 +280,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
   double zq = 0.0;
   if (threadIdx.x < T) {
     const double* Li = lds_x + threadIdx.x * PLD;
-    const double* w = po.omega(m);
-    for (int q = 0; q <= (int)threadIdx.x; ++q) zq += Li[q] * w[q];
+    for (int q = 0; q <= (int)threadIdx.x; ++q) zq += Li[q] * wsh[q];
     po.zw()[threadIdx.x] = zq;
   }
   const double nrm = block_sum(zq * zq, red);
@@ -332,18 +333,32 @@ __global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap
       Post pc = post_of(P, S, m, ch[c]);
       const double* Zk = pc.Z(k);
       const double* zw = pc.zw();
+      double zk[T / 4], zv[T / 4];   // rows wave, wave + 4, ...: all loads issued first
+#pragma unroll
+      for (int j = 0; j < T / 4; ++j) {
+        zk[j] = Zk[(wave_id() + 4 * j) * T + col];
+        zv[j] = zw[wave_id() + 4 * j];
+      }
       if (wave_id() == 0) w += pc.omega(k)[col];
-      for (int q = wave_id(); q < T; q += 4) w -= Zk[q * T + col] * zw[q];
+#pragma unroll
+      for (int j = 0; j < T / 4; ++j) w -= zk[j] * zv[j];
     }
     w = wave_col_sum(w, lds);
     if (threadIdx.x < T) pp.omega(k)[threadIdx.x] = w;
   }
   if (kl == 0 && threadIdx.x == 0) {
+    double dv[16], uv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < nch) {
+        Post pc = post_of(P, S, m, ch[c]);
+        dv[c] = *pc.d();
+        uv[c] = *pc.u();
+      }
     double dsum = 0.0, usum = 0.0;
     for (int c = 0; c < nch; ++c) {
-      Post pc = post_of(P, S, m, ch[c]);
-      dsum += *pc.d();
-      usum += *pc.u();
+      dsum += dv[c];
+      usum += uv[c];
     }
     *pp.d() = dsum;
     *pp.u() = usum;

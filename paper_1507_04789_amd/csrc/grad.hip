@@ -88,10 +88,22 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
     acc_store(acc, gr.Tsum(0, 0) + (int64_t)l * TT, T);
   }
   if (threadIdx.x < T) {
+    // q from threadIdx.x up; each batch of 16 rows is loaded before it is used
     double s = 0.0;
     const double* Li = po.Lti();
     const double* zw = po.zw();
-    for (int q = threadIdx.x; q < T; ++q) s += Li[q * T + threadIdx.x] * zw[q];
+    for (int q0 = 0; q0 < T; q0 += 16) {
+      if (q0 + 15 < (int)threadIdx.x) continue;
+      double lv[16], zv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        lv[j] = Li[(q0 + j) * T + threadIdx.x];
+        zv[j] = zw[q0 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (q0 + j >= (int)threadIdx.x) s += lv[j] * zv[j];
+    }
     vw[threadIdx.x] = s;
   }
   __syncthreads();
@@ -445,9 +457,15 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
   const double* X = knots_of(P, m, i);
   // Lbar = -tril(Tsum^{m,m})
   const double* Tmm = gr.Tsum(m, m);
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    int r = e >> 6, q = e & 63;
-    sc[e] = (q <= r) ? -Tmm[e] : 0.0;
+  {
+    double v[TT / NT];   // all loads issued before the first store
+#pragma unroll
+    for (int j = 0; j < TT / NT; ++j) v[j] = Tmm[threadIdx.x + j * NT];
+#pragma unroll
+    for (int j = 0; j < TT / NT; ++j) {
+      const int e = threadIdx.x + j * NT, r = e >> 6, q = e & 63;
+      sc[e] = (q <= r) ? -v[j] : 0.0;
+    }
   }
   __syncthreads();
   Acc acc;

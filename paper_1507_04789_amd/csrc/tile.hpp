@@ -70,74 +70,6 @@ __device__ __forceinline__ void acc_store(const Acc& a, double* C, int ldc) {
 
 enum class Op { N, T };
 
-// acc += alpha * opA(A) * opB(B) over K (multiple of KC), 64x64 output.
-//   opA = N: A(i,k) = A[i*lda + k]  ;  opA = T: A(i,k) = A[k*lda + i]
-//   opB = T: B(k,j) = B[j*ldb + k]  ;  opB = N: B(k,j) = B[k*ldb + j]
-// Two LDS stages: the global loads of chunk c+1 are in flight while the
-// MFMAs of chunk c run; one barrier per chunk.  Ends with a barrier, so the
-// caller may overwrite A or B afterwards.
-template <Op OA>
-__device__ __forceinline__ d4 fetch(const double* p, int ld, int k0) {
-  const int t = threadIdx.x;
-  if (OA == Op::N) return *(const d4*)(p + (int64_t)(t >> 2) * ld + k0 + (t & 3) * 4);
-  return *(const d4*)(p + (int64_t)(k0 + (t >> 4)) * ld + (t & 15) * 4);
-}
-template <Op OA>
-__device__ __forceinline__ void stash(double* s, d4 v) {
-  const int t = threadIdx.x;
-  if (OA == Op::N) {
-    const int i = t >> 2, kq = (t & 3) * 4;
-    s[(kq + 0) * SLD + i] = v[0];
-    s[(kq + 1) * SLD + i] = v[1];
-    s[(kq + 2) * SLD + i] = v[2];
-    s[(kq + 3) * SLD + i] = v[3];
-  } else {
-    *(d4*)(s + (t >> 4) * SLD + (t & 15) * 4) = v;
-  }
-}
-
-template <Op OA, Op OB>
-__device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const double* B, int ldb, int K,
-                                     double alpha, double* lds) {
-  constexpr Op LB = (OB == Op::T) ? Op::N : Op::T;   // B(k,j) = B^T(j,k): same loader roles
-  const int w = wave_id(), l = lane_id();
-  const int ia = 32 * (w >> 1) + (l & 15);
-  const int jb = 32 * (w & 1) + (l & 15);
-  const int kr = l >> 4;
-  const int nch = K / KC;
-  d4 va = fetch<OA>(A, lda, 0);
-  d4 vb = fetch<LB>(B, ldb, 0);
-  stash<OA>(lds, va);
-  stash<LB>(lds + KC * SLD, vb);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    double* sA = lds + (c & 1) * 2 * KC * SLD;
-    double* sB = sA + KC * SLD;
-    const bool more = c + 1 < nch;
-    if (more) {
-      va = fetch<OA>(A, lda, (c + 1) * KC);
-      vb = fetch<LB>(B, ldb, (c + 1) * KC);
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const double* ra = sA + (kk + kr) * SLD;
-      const double* rb = sB + (kk + kr) * SLD;
-      double a0 = alpha * ra[ia], a1 = alpha * ra[ia + 16];
-      double b0 = rb[jb], b1 = rb[jb + 16];
-      acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
-      acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
-      acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
-      acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
-    }
-    if (more) {
-      double* nA = lds + ((c + 1) & 1) * 2 * KC * SLD;
-      stash<OA>(nA, va);
-      stash<LB>(nA + KC * SLD, vb);
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------
 // multi-segment GEMM: acc += sum_s alpha_s * opA_s(A_s) * opB_s(B_s), each
 // segment a 64x64xK_s product (K_s = 16 * nch_s, nch_s in 1..4).  The
@@ -390,6 +322,17 @@ __device__ __forceinline__ Seg seg(const double* A, int lda, const double* B, in
   return Seg{A, B, lda, ldb, OA == Op::T, OB == Op::N, nch, alpha};
 }
 
+// acc += alpha * opA(A) * opB(B) over K (multiple of KC), 64x64 output:
+//   opA = N: A(i,k) = A[i*lda + k]  ;  opA = T: A(i,k) = A[k*lda + i]
+//   opB = T: B(k,j) = B[j*ldb + k]  ;  opB = N: B(k,j) = B[k*ldb + j]
+// One segment of gemm_segs2 (two k-chunks in flight).  Ends with a barrier,
+// so the caller may overwrite A or B afterwards.
+template <Op OA, Op OB>
+__device__ __forceinline__ void gemm(Acc& acc, const double* A, int lda, const double* B, int ldb, int K,
+                                     double alpha, double* lds) {
+  gemm_segs2(acc, 1, [&](int) { return seg<OA, OB>(A, lda, B, ldb, alpha, K / KC); }, lds);
+}
+
 // ---------------------------------------------------------------------------
 // factorisation of one 64x64 tile in LDS (pitch PLD)
 // ---------------------------------------------------------------------------
@@ -403,10 +346,18 @@ __device__ __forceinline__ void acc_to_lds(const Acc& a, double* s) {
       for (int v = 0; v < 4; ++v) s[acc_row(bi, v) * PLD + acc_col(bj)] = a.c[bi][bj][v];
 }
 
+// all 16 loads of a thread are issued before the first LDS store
 __device__ __forceinline__ void tile_to_lds(const double* C, int ldc, double* s) {
-  for (int e = threadIdx.x; e < TT; e += NT) {
-    int i = e >> 6, j = e & 63;
-    s[i * PLD + j] = C[(int64_t)i * ldc + j];
+  double v[TT / NT];
+#pragma unroll
+  for (int q = 0; q < TT / NT; ++q) {
+    const int e = threadIdx.x + q * NT;
+    v[q] = C[(int64_t)(e >> 6) * ldc + (e & 63)];
+  }
+#pragma unroll
+  for (int q = 0; q < TT / NT; ++q) {
+    const int e = threadIdx.x + q * NT;
+    s[(e >> 6) * PLD + (e & 63)] = v[q];
   }
 }
 
@@ -499,48 +450,70 @@ __device__ __forceinline__ double rsqrt_d(double p) {
 }
 
 // Lower Cholesky of the 16x16 block D (pitch PLD) and the inverse of the
-// factor in one right-looking sweep, by lanes 0..15 of one wave: lane i keeps
-// row i of the working block (a) and of the inverse (x) in registers.  Step j
-// takes the pivot from lane j, forms column j of the factor, then updates the
-// trailing columns with column j (a_ik -= L_ij L_kj, k > j) and the inverse
-// rows below j with row j of the inverse (x_i -= L_ij x_j, the forward
-// substitution of L X = I); both operands are broadcast by readlane, so the
-// loop touches no LDS.  On return D holds L (zero above the diagonal) and X
-// (pitch ldx) holds L^{-1}.  Returns 0 if a pivot was not positive (the
-// outputs then carry NaN).
+// factor in one right-looking sweep by one wave: lane 16 q + i keeps columns
+// 4q..4q+3 of row i of the working block (a) and of the inverse (x) in
+// registers.  Step j takes the pivot a_jj by readlane, forms column j of the
+// factor, broadcasts it and row j of the inverse through LDS (a wave's LDS
+// accesses complete in order; lanes that own nothing write to slots of their
+// own), then updates the trailing columns (a_ik -= L_ij L_kj, k > j) and the
+// inverse rows below j (x_i -= L_ij x_j, the forward substitution of
+// L X = I).  The next pivot, a_{j+1,j+1} - L_{j+1,j}^2, is formed right after
+// column j, before the broadcast.  No branches: a pivot that is not positive
+// makes the reciprocal square root NaN, and the NaN spreads.  On return D
+// holds L (zero above the diagonal) and X (pitch ldx) holds L^{-1}.  Returns
+// 0 if a pivot was not positive.
 __device__ __forceinline__ int potrf_trtri16(double* D, double* X, int ldx) {
-  const int i = lane_id();
-  const bool own = i < 16;
-  double a[16], x[16];
+  __shared__ double colb[16 + 64], xrow[16 + 4 * 64];
+  const int l = lane_id(), i = l & 15, q = l >> 4;
+  double a[4], x[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    a[k] = own ? D[i * PLD + k] : 0.0;
-    x[k] = (i == k) ? 1.0 : 0.0;
+  for (int c = 0; c < 4; ++c) {
+    a[c] = D[i * PLD + 4 * q + c];
+    x[c] = (i == 4 * q + c) ? 1.0 : 0.0;
   }
   int ok = 1;
+  double p = readlane_d(a[0], 0);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double p = readlane_d(a[j], j);
+    const int jq = j >> 2, jc = j & 3;
     ok &= (p > 0.0) ? 1 : 0;
-    const double y = (p > 0.0) ? rsqrt_d(p) : __builtin_nan("");
-    const double l = (i > j) ? a[j] * y : (i == j ? p * y : 0.0);   // L_ij
-    a[j] = l;
+    const double y = rsqrt_d(p);   // NaN unless p > 0
+    const double lv = (i > j) ? a[jc] * y : (i == j ? p * y : 0.0);   // L_ij in the lanes of quarter jq
+    double pn = 0.0;
+    if (j < 15) {                  // the next pivot, with the same fma as the update below
+      const int j1 = j + 1;
+      if ((j1 >> 2) == jq) {
+        pn = readlane_d(fma(-lv, lv, a[j1 & 3]), 16 * jq + j1);
+      } else {
+        const double lx = readlane_d(lv, 16 * jq + j1);
+        pn = readlane_d(fma(-lx, lx, a[0]), 16 * (j1 >> 2) + j1);
+      }
+    }
+    a[jc] = (q == jq) ? lv : a[jc];
+    colb[q == jq ? i : 16 + l] = lv;
     // row j of the inverse is final once scaled by 1 / L_jj
     const double sj = (i == j) ? y : 1.0;
+    double* xw = xrow + (i == j ? 4 * q : 16 + 4 * l);
 #pragma unroll
-    for (int c = 0; c <= j; ++c) x[c] *= sj;
-    const double lb = (i > j) ? l : 0.0;
-#pragma unroll
-    for (int k = j + 1; k < 16; ++k) a[k] = fma(-lb, readlane_d(l, k), a[k]);
-#pragma unroll
-    for (int c = 0; c <= j; ++c) x[c] = fma(-lb, readlane_d(x[c], j), x[c]);
-  }
-  if (own) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      D[i * PLD + k] = (k <= i) ? a[k] : 0.0;
-      X[i * ldx + k] = x[k];
+    for (int c = 0; c < 4; ++c) {
+      x[c] *= sj;
+      xw[c] = x[c];
     }
+    __builtin_amdgcn_wave_barrier();
+    const double lb = (i > j) ? colb[i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double lbc = (4 * q + c > j) ? lb : 0.0;
+      a[c] = fma(-lbc, colb[4 * q + c], a[c]);
+      x[c] = fma(-lb, xrow[4 * q + c], x[c]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    p = pn;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    D[i * PLD + 4 * q + c] = (4 * q + c <= i) ? a[c] : 0.0;
+    X[i * ldx + 4 * q + c] = x[c];
   }
   return ok;
 }
