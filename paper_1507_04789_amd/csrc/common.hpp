@@ -109,10 +109,12 @@ __device__ inline double potrf_tiles(double* base, double* dinv, int nb, int nv,
       acc_load(acc, X, T);
       gemm_segs2(acc, jb,
                 [&](int k) { return seg<Op::N, Op::T>(Li + (int64_t)k * TT, T, Lj + (int64_t)k * TT, T, -1.0); }, lds);
-      acc_store(acc, X, T);
+      // L_{ib,jb} = (updated tile) L_jb^{-T}: the updated tile stays in LDS,
+      // the inverse streams through lds_x (free once the diagonal step is done)
+      acc_to_lds(acc, lds);
       __syncthreads();
       acc_zero(acc);
-      gemm_segs2(acc, 1, [&](int) { return seg<Op::N, Op::T>(X, T, dinv + (int64_t)jb * TT, T, 1.0); }, lds);
+      gemm_lds_a(acc, lds, dinv + (int64_t)jb * TT, T, false, 1.0, lds_x);
       acc_store(acc, X, T);
       __syncthreads();
     }

@@ -137,11 +137,15 @@ __global__ __launch_bounds__(NT, 2) void k_leaf_potrf(DevPlan P, TaskMap tm) {
 // Y = L_Sigma^{-1} X for one column plane of one leaf (forward substitution
 // by tiles with the inverted diagonal tiles).  The data plane M holds zc
 // nonzero columns (a multiple of 16: z and the trend columns); the others
-// stay zero and are not multiplied.
+// stay zero and are not multiplied.  RES (the launch for the large leaves):
+// after the updates, the right-hand side tile stays in LDS for the product
+// with the diagonal inverse instead of a round trip through global memory
+// (same products in the same order, so the same bits; more LDS per block).
+template <bool RES>
 __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, int zc, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[RES ? LDS_SWEEP : LDS_DOUBLES];
   const int th = blockIdx.y;
   const int32_t* task = P.trsm_tasks + 2 * tk0;
   const int leaf = task[0], cpl = task[1];
@@ -163,6 +167,15 @@ __global__ __launch_bounds__(NT, 4) void k_leaf_trsm(DevPlan P, int zc, TaskMap 
       gemm_segs2(acc, ib,
                 [&](int jb) { return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + jb) * TT, T, Y + (int64_t)jb * TT, T, -1.0); },
                 lds, mr, nc);
+      if (RES) {
+        acc_to_lds(acc, lds);
+        __syncthreads();
+        acc_zero(acc);
+        gemm_lds_b(acc, dinv + (int64_t)ib * TT, T, false, lds, 1.0, lds + LDS_DOUBLES, mr, nc);
+        acc_store(acc, Y + (int64_t)ib * TT, T);
+        __syncthreads();
+        continue;
+      }
       acc_store(acc, Y + (int64_t)ib * TT, T);
       __syncthreads();
       R = Y + (int64_t)ib * TT;
@@ -451,7 +464,7 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
               k_leaf_potrf, f0, f1);
   }
   run.tuned(F_TRSM, MAP_GROUPED, factor ? "leaf_trsm" : "leaf_trsm_re", -1,
-            factor ? H.trsm_flops_big(f1) - H.trsm_flops_big(f0) : 0.0, M + 1, nullptr, k_leaf_trsm, f0 * (M + 1),
+            factor ? H.trsm_flops_big(f1) - H.trsm_flops_big(f0) : 0.0, M + 1, nullptr, k_leaf_trsm<false>, f0 * (M + 1),
             f1 * (M + 1), zcols(px));
   return hipGetLastError();
 }
@@ -501,12 +514,13 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
     Runner rs{P, nth, side->s, false, H.prof, H.tune};
     const double fpb = H.potrf_flops_big(nbig), ftb = H.trsm_flops_big(nbig);
     rs.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf_big", -1, fpb, 1, nullptr, k_leaf_potrf, 0, nbig);
-    rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm, 0, nbig * (M + 1), zcols(px));
+    rs.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm_big", -1, ftb, M + 1, nullptr, k_leaf_trsm<true>, 0, nbig * (M + 1),
+             zcols(px));
     if ((e = hipEventRecord(side->big, side->s)) != hipSuccess) return e;
   }
   run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, F.potrf - H.potrf_flops_big(nbig), 1, nullptr, k_leaf_potrf, nbig,
             nfac);
-  run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm,
+  run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm<false>,
             nbig * (M + 1), ntrsm, zcols(px));
   return hipGetLastError();
 }

@@ -316,6 +316,50 @@ __device__ __forceinline__ void gemm_lds_a(Acc& acc, const double* A, const doub
   }
 }
 
+// acc += alpha * A * B for one 64x64x64 product whose B operand is already
+// in LDS (B(k, j) at Bs[k * PLD + j], as acc_to_lds leaves a tile) and whose
+// A operand is in global memory (A(i, k) = A[k * lda + i] when ak, else
+// A[i * lda + k]); only A streams, through `stage` (2 * KC * SLD doubles,
+// disjoint from Bs).  Output blocks at or beyond mrows / ncols are not
+// multiplied.  The products are issued in the order gemm_segs uses for a
+// single segment, so the result is the same to the bit.
+__device__ __forceinline__ void gemm_lds_b(Acc& acc, const double* A, int lda, bool ak, const double* Bs,
+                                           double alpha, double* stage, int mrows = T, int ncols = T) {
+  const int w = wave_id(), l = lane_id();
+  const int ia = 32 * (w >> 1) + (l & 15);
+  const int jb = 32 * (w & 1) + (l & 15);
+  const int kr = l >> 4;
+  const bool row0 = 32 * (w >> 1) < mrows, row1 = 32 * (w >> 1) + 16 < mrows;
+  const bool col0 = 32 * (w & 1) < ncols, col1 = 32 * (w & 1) + 16 < ncols;
+  d4 va = fetch_rt(A, lda, 0, ak);
+  stash_rt(stage, va, ak);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < T / KC; ++c) {
+    const bool more = c + 1 < T / KC;
+    if (more) va = fetch_rt(A, lda, (c + 1) * KC, ak);
+    const double* sA = stage + (c & 1) * KC * SLD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int k = c * KC + kk + kr;
+      const double* ra = sA + (kk + kr) * SLD;
+      const double b0 = Bs[k * PLD + jb], b1 = Bs[k * PLD + jb + 16];
+      if (row0) {
+        const double a0 = alpha * ra[ia];
+        if (col0) acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+        if (col1) acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+      }
+      if (row1) {
+        const double a1 = alpha * ra[ia + 16];
+        if (col0) acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+        if (col1) acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+      }
+    }
+    if (more) stash_rt(stage + ((c + 1) & 1) * KC * SLD, va, ak);
+    __syncthreads();
+  }
+}
+
 // Seg for one 64x64x64 block product in the gemm<> operand conventions
 template <Op OA, Op OB>
 __device__ __forceinline__ Seg seg(const double* A, int lda, const double* B, int ldb, double alpha, int nch = T / KC) {
@@ -524,21 +568,36 @@ __device__ __forceinline__ int potrf_trtri16(double* D, double* X, int ldx) {
 // Diagonal blocks are factored and inverted by wave 0; panel and trailing
 // updates and the off-diagonal blocks of the inverse
 //   X_ii = L_ii^{-1},  X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj  (i > j)
-// run on MFMA across the four waves.  On return s holds L (upper part zero).
-// Returns false (uniformly) if a pivot was not positive; the factor and the
-// inverse then carry NaN.
+// run on MFMA across the four waves.  Block row i of the inverse needs only
+// the factor's columns left of i and the rows of the inverse above it, so
+// rows 1 and 2 are formed by waves 1 and 2 while wave 0 factors the next
+// diagonal block, and row 3 at the end.  On return s holds L (upper part
+// zero).  Returns false (uniformly) if a pivot was not positive; the factor
+// and the inverse then carry NaN.
 __device__ inline bool potrf_trtri(double* s, double* sx, double* Linv) {
   __shared__ int ok_all;
+  __shared__ double tsc[4][16 * 16];   // per-wave partial sum of an inverse block
   const int w = wave_id();
+  // X_ij (i > j) for block row ib by the calling wave
+  auto inv_block = [&](int ib, int jb) {
+    d4 t = {0.0, 0.0, 0.0, 0.0};             // t = sum_{k=j}^{i-1} L_ik X_kj
+    for (int kb = jb; kb < ib; ++kb)
+      mfma_ab(t, s + 16 * ib * PLD + 16 * kb, PLD, sx + 16 * kb * PLD + 16 * jb, PLD, 16, 1.0);
+    blk_store(t, tsc[w], 16);                // one wave: its LDS accesses complete in order
+    __builtin_amdgcn_wave_barrier();
+    d4 x = {0.0, 0.0, 0.0, 0.0};             // X_ij = -X_ii t
+    mfma_ab(x, sx + 16 * ib * PLD + 16 * ib, PLD, tsc[w], 16, 16, -1.0);
+    blk_store(x, sx + 16 * ib * PLD + 16 * jb, PLD);
+  };
   if (threadIdx.x == 0) ok_all = 1;
-  for (int e = threadIdx.x; e < TT; e += NT) sx[(e >> 6) * PLD + (e & 63)] = 0.0;
-  __syncthreads();
   for (int kb = 0; kb < 4; ++kb) {
     double* Dk = s + 16 * kb * PLD + 16 * kb;
     double* Xk = sx + 16 * kb * PLD + 16 * kb;
     if (w == 0) {
       const int ok = potrf_trtri16(Dk, Xk, PLD);
       if (lane_id() == 0 && !ok) ok_all = 0;
+    } else if (w < kb) {                       // inverse row kb - 1, block w - 1
+      inv_block(kb - 1, w - 1);
     }
     __syncthreads();
     const int ib = kb + 1 + w;                 // panel: L_ik = A_ik X_kk^T
@@ -559,30 +618,19 @@ __device__ inline bool potrf_trtri(double* s, double* sx, double* Linv) {
           mfma_abt(acc, s + 16 * i2 * PLD + 16 * kb, PLD, s + 16 * j2 * PLD + 16 * kb, PLD, 16, -1.0);
           blk_store(acc, Aij, PLD);
         }
-    __syncthreads();
+    if (kb < 3) __syncthreads();
   }
-  // zero the strictly upper blocks of L
+  if (w < 3) inv_block(3, w);                  // inverse row 3
+  // zero the strictly upper blocks of L and of the inverse (callers use both
+  // LDS tiles whole)
   for (int e = threadIdx.x; e < TT; e += NT) {
     const int i = e >> 6, j = e & 63;
-    if ((j >> 4) > (i >> 4)) s[i * PLD + j] = 0.0;
-  }
-  for (int ib = 1; ib < 4; ++ib) {
-    const int jb = w;
-    double* Xij = sx + 16 * ib * PLD + 16 * jb;
-    if (jb < ib) {                             // t = sum_{k=j}^{i-1} L_ik X_kj
-      d4 t = {0.0, 0.0, 0.0, 0.0};
-      for (int kb = jb; kb < ib; ++kb)
-        mfma_ab(t, s + 16 * ib * PLD + 16 * kb, PLD, sx + 16 * kb * PLD + 16 * jb, PLD, 16, 1.0);
-      blk_store(t, Xij, PLD);
+    if ((j >> 4) > (i >> 4)) {
+      s[i * PLD + j] = 0.0;
+      sx[i * PLD + j] = 0.0;
     }
-    __syncthreads();
-    if (jb < ib) {                             // X_ij = -X_ii t
-      d4 x = {0.0, 0.0, 0.0, 0.0};
-      mfma_ab(x, sx + 16 * ib * PLD + 16 * ib, PLD, Xij, PLD, 16, -1.0);
-      blk_store(x, Xij, PLD);
-    }
-    __syncthreads();
   }
+  __syncthreads();
   for (int e = threadIdx.x; e < TT; e += NT) Linv[e] = sx[(e >> 6) * PLD + (e & 63)];
   __syncthreads();
   return ok_all != 0;
