@@ -453,8 +453,11 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
   double* reg = prior_reg(P, S, m, i);
   const double* L = reg + (int64_t)m * TT;
   const double* Li = reg + (int64_t)(m + 1) * TT;
-  double* sc = gr.scratch();
   const double* X = knots_of(P, m, i);
+  // The Cholesky adjoint keeps its intermediates in LDS (pitch PLD): each
+  // product takes the previous result from there and streams its other
+  // operand through the stage behind it.
+  double* stage = lds + LDS_DOUBLES;
   // Lbar = -tril(Tsum^{m,m})
   const double* Tmm = gr.Tsum(m, m);
   {
@@ -464,13 +467,13 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
 #pragma unroll
     for (int j = 0; j < TT / NT; ++j) {
       const int e = threadIdx.x + j * NT, r = e >> 6, q = e & 63;
-      sc[e] = (q <= r) ? -v[j] : 0.0;
+      lds[r * PLD + q] = (q <= r) ? -v[j] : 0.0;
     }
   }
   __syncthreads();
   Acc acc;
   acc_zero(acc);
-  gemm<Op::T, Op::N>(acc, L, T, sc, T, T, 1.0, lds);     // L' Lbar
+  gemm_lds_b(acc, L, T, true, lds, 1.0, stage);          // L' Lbar
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -481,17 +484,28 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
         if (q > r) acc.c[bi][bj][v] = 0.0;
         else if (q == r) acc.c[bi][bj][v] *= 0.5;       // Phi
       }
-  acc_store(acc, sc, T);
+  acc_to_lds(acc, lds);
   __syncthreads();
   acc_zero(acc);
-  gemm<Op::N, Op::N>(acc, sc, T, Li, T, T, 1.0, lds);    // Phi L^{-1}
-  acc_store(acc, sc, T);
+  gemm_lds_a(acc, lds, Li, T, true, 1.0, stage);        // Phi L^{-1}
+  acc_to_lds(acc, lds);
   __syncthreads();
   acc_zero(acc);
-  gemm<Op::T, Op::N>(acc, Li, T, sc, T, T, 1.0, lds);    // L^{-T} Phi L^{-1}
-  acc_store(acc, sc, T);
-  symmetrize(sc);                                        // Wbar^m
-  acc_load(acc, sc, T);
+  gemm_lds_b(acc, Li, T, true, lds, 1.0, stage);        // L^{-T} Phi L^{-1}
+  acc_to_lds(acc, lds);
+  __syncthreads();
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)                         // Wbar^m = sym(.)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_row(bi, v), q = acc_col(bj);
+        acc.c[bi][bj][v] = 0.5 * (lds[r * PLD + q] + lds[q * PLD + r]);
+      }
+  __syncthreads();
+  acc_to_lds(acc, lds);
+  __syncthreads();
   double g[3] = {0.0, 0.0, 0.0};
   acc_cov_contract(acc, X, P.rl[m], X, P.rl[m], c, false, g);
   // W^-bar^k = -Tsum^{m,k} - 2 Wbar^m W^^k_R, k < m
@@ -501,7 +515,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) acc.c[bi][bj] = -acc.c[bi][bj];
-    gemm<Op::N, Op::N>(acc, sc, T, reg + (int64_t)k * TT, T, T, -2.0, lds);
+    gemm_lds_a(acc, lds, reg + (int64_t)k * TT, T, true, -2.0, stage);
     acc_store(acc, gr.Wbar(k), T);
   }
   __syncthreads();
