@@ -43,19 +43,6 @@ __device__ __forceinline__ const double* wbar_omega_of(const DevPlan& P, double*
   return grad_of(P, S, k, ancestor(P, lev, idx, k)).wbar_omega();
 }
 
-// symmetrise a tile in global memory in place (tile written by this block)
-__device__ void symmetrize(double* C) {
-  __syncthreads();
-  double v[TT / NT];
-  for (int q = 0; q < TT / NT; ++q) {
-    int e = threadIdx.x + q * NT, i = e >> 6, j = e & 63;
-    v[q] = 0.5 * (C[i * T + j] + C[j * T + i]);
-  }
-  __syncthreads();
-  for (int q = 0; q < TT / NT; ++q) C[threadIdx.x + q * NT] = v[q];
-  __syncthreads();
-}
-
 __device__ void write_partial(const DevPlan& P, double* S, int64_t slot, double g[3], double* red) {
   double a = block_sum(g[0], red);
   double b = block_sum(g[1], red);
@@ -110,7 +97,7 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
   const double* V0 = gr.Tsum(0, 0);
   for (int l = 0; l < m; ++l) {       // Xbar_l = -2 sum_k V_k S^{k,l} - v_w wbar^l'
     acc_zero(acc);
-    gemm_segs(acc, m, [&](int k) { return seg_S(P, S, V0 + (int64_t)k * TT, k, l, m, i, -2.0); }, lds);
+    gemm_segs2(acc, m, [&](int k) { return seg_S(P, S, V0 + (int64_t)k * TT, k, l, m, i, -2.0); }, lds);
     const double* wb = wbar_omega_of(P, S, l, m, i);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -135,7 +122,7 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
   __syncthreads();
   // Pbar = -1/2 (sum_l Xbar_l V_l' + xbar_w v_w' + Lt^{-T} Lt^{-1})
   acc_zero(acc);
-  gemm_segs(acc, m + 1, [&](int l) {
+  gemm_segs2(acc, m + 1, [&](int l) {
     if (l < m) return seg<Op::N, Op::T>(gr.G(l), T, V0 + (int64_t)l * TT, T, -0.5);
     return seg<Op::T, Op::N>(po.Lti(), T, po.Lti(), T, -0.5);
   }, lds);
@@ -146,8 +133,15 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc.c[bi][bj][v] -= 0.5 * xw[acc_row(bi, v)] * vw[acc_col(bj)];
-  acc_store(acc, gr.G(m), T);
-  symmetrize(gr.G(m));
+  // G(m) = sym(Pbar), the transpose read from LDS
+  acc_to_lds(acc, lds);
+  __syncthreads();
+  double* Gm = gr.G(m);
+#pragma unroll
+  for (int q = 0; q < TT / NT; ++q) {
+    const int e = threadIdx.x + q * NT, r = e >> 6, cc = e & 63;
+    Gm[e] = 0.5 * (lds[r * PLD + cc] + lds[cc * PLD + r]);
+  }
 }
 
 // ---------------------------------------------------------------- leaves
@@ -315,11 +309,20 @@ __global__ __launch_bounds__(NT) void k_rleaf_sbar(DevPlan P, const double* thet
     return seg<Op::T, Op::N>(li(kb, bi), T, li(kb, bj), T, -0.5);
   }, lds, round16(nvi), round16(nvj));
   double* out = S + P.off_sbar + (P.leaf_soff[leaf] + (int64_t)bi * nb + bj) * TT;
-  acc_store(acc, out, T);
-  if (bi == bj) {
-    symmetrize(out);
-    acc_load(acc, out, T);
+  if (bi == bj) {      // a diagonal tile is symmetrised, the transpose read from LDS
+    acc_to_lds(acc, lds);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_row(a, v), q = acc_col(b);
+          acc.c[a][b][v] = 0.5 * (lds[r * PLD + q] + lds[q * PLD + r]);
+        }
   }
+  acc_store(acc, out, T);
   double g[3] = {0.0, 0.0, 0.0};
   acc_cov_contract(acc, P.obs_xy + 2 * pi, nvi, P.obs_xy + 2 * pj, nvj, cp, bi == bj, g);
   const double wgt = (bi == bj) ? 1.0 : 2.0;   // lower tiles stand for both triangles
