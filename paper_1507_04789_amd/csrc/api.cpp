@@ -157,6 +157,9 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   if (overlap && (e = ensure_side(H)) != hipSuccess) return e;
   const Side sd = side_of(H);
   const Side* side = overlap ? &sd : nullptr;
+  // the partial sums are cleared up front, where the GPU is nearly idle,
+  // rather than in the reverse posterior chain
+  if ((e = launch_zero_gpart(*H, nth, st)) != hipSuccess) return e;
   if ((e = launch_forward_front(*H, y, theta, nth, st, side, y_stride)) != hipSuccess) return e;
   const bool on_side = side && H->side_solves > 0;
   if (!on_side) {
@@ -185,7 +188,7 @@ hipError_t launch_grad_all(mra_plan_s* H, const double* y, const double* theta, 
   }, &ctx, false};
   ForkHook* hk = on_side ? &hook : nullptr;
   if ((e = launch_forward_back(*H, nth, ll, st, side, hk)) != hipSuccess) return e;
-  if ((e = launch_grad_post(*H, nth, st, hk)) != hipSuccess) return e;
+  if ((e = launch_grad_post(*H, nth, st, hk, false)) != hipSuccess) return e;
   if (on_side && (e = hipStreamWaitEvent(st, sd.join, 0)) != hipSuccess) return e;
   return launch_grad_rest(*H, y, y_stride, theta, nth, g, gy, st, on_side ? sd.join2 : nullptr);
 }

@@ -611,16 +611,25 @@ hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st, h
   return hipGetLastError();
 }
 
-// the posterior reverse pass (after the forward log-likelihood)
-hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook) {
+// clear the gradient partial sums (any time before the reverse pass)
+hipError_t launch_zero_gpart(const mra_plan_s& H, int nth, hipStream_t st) {
+  const DevPlan& P = H.dp;
+  const int M = P.M;
+  const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
+  const int64_t nslot = P.n_sig_tiles + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
+  hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
+  return hipGetLastError();
+}
+
+// the posterior reverse pass (after the forward log-likelihood); clears the
+// partial sums first unless the caller has done so
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook, bool zero_partials) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
-  const int64_t nrow = (int64_t)H.row_tasks.size() / 2;
-  const int64_t nslot = P.n_sig_tiles + nrow + (M > 0 ? P.reg_base[M - 1] + P.nreg[M - 1] : 0);
-  hipLaunchKernelGGL(k_zero_gpart, dim3(64, nth), dim3(NT), 0, st, P, nslot);
   hipError_t e;
+  if (zero_partials && (e = launch_zero_gpart(H, nth, st)) != hipSuccess) return e;
   for (int m = 0; m < M; ++m) {
     run.tuned(F_RPOST, MAP_IDENTITY, "rpost", m, F.rpost[m], 1, nullptr, k_rpost, 0, H.nact_post(m), m);
     if (hook && (e = hook->at(M + 2 + m)) != hipSuccess) return e;

@@ -208,7 +208,9 @@ hipError_t launch_forward_back(const mra_plan_s& H, int nth, double* out_loglik,
                                const Side* side = nullptr, ForkHook* hook = nullptr);
 // after_v (may be null) is recorded on st once V is written, before L^{-1}
 hipError_t launch_grad_leafsolve(const mra_plan_s& H, int nth, hipStream_t st, hipEvent_t after_v = nullptr);
-hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook = nullptr);
+hipError_t launch_zero_gpart(const mra_plan_s& H, int nth, hipStream_t st);
+hipError_t launch_grad_post(const mra_plan_s& H, int nth, hipStream_t st, ForkHook* hook = nullptr,
+                            bool zero_partials = true);
 // grad_y (may be null): [nth][n] gradient of the log-likelihood with respect
 // to the data, in the caller's order
 // wait_linv (may be null): event to wait for before the first use of L^{-1}
