@@ -167,8 +167,8 @@ def _csv(path):
 
 
 def _short(name: str) -> str:
-    m = re.match(r"^mra::(k_\w+)", name)
-    return m.group(1)[2:] if m else name[:40]
+    m = re.match(r"^(?:void )?mra::k_(\w+)(<\w+>)?", name)
+    return m.group(1) + (m.group(2) or "") if m else name[:40]
 
 
 def summarize_profiles(root: str, copy_bytes: int):
@@ -272,7 +272,7 @@ def _timeline(path: str, step: int = 2):
     and end relative to the step's first launch, with its hardware queue.
     Step 2 of a `--steps 3 --warmup 1` run is the second timed graph replay
     (step 0 is the warm-up, steps 4..6 the eager profiled pass)."""
-    rows = [r for r in _csv(path) if r["Kernel_Name"].startswith("mra::")]
+    rows = [r for r in _csv(path) if "mra::k_" in r["Kernel_Name"]]
     starts = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "init"]
     if len(starts) <= step:
         return []

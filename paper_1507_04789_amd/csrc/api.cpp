@@ -54,7 +54,7 @@ mra_status collect_failures(mra_plan_s* H, int nth, hipStream_t st) {
 hipError_t ensure_side(mra_plan_s* H) {
   if (H->side_stream) return hipSuccess;
   hipStream_t s2;
-  constexpr int NEV = 5;
+  constexpr int NEV = 7;
   hipEvent_t ev[NEV] = {};
   hipError_t e;
   for (int i = 0; i < NEV; ++i)
@@ -72,6 +72,8 @@ hipError_t ensure_side(mra_plan_s* H) {
   H->ev_fork2 = ev[2];
   H->ev_join = ev[3];
   H->ev_join2 = ev[4];
+  H->ev_gfork = ev[5];
+  H->ev_gath = ev[6];
   return hipSuccess;
 }
 
@@ -79,8 +81,9 @@ hipError_t ensure_side(mra_plan_s* H) {
 bool uses_side(const mra_plan_s* H) { return !(H->cfg.flags & MRA_PLAIN) && H->nchunks == 1; }
 
 Side side_of(const mra_plan_s* H) {
-  return Side{(hipStream_t)H->side_stream, (hipEvent_t)H->ev_fork, (hipEvent_t)H->ev_big, (hipEvent_t)H->ev_fork2,
-              (hipEvent_t)H->ev_join, (hipEvent_t)H->ev_join2};
+  return Side{(hipStream_t)H->side_stream, (hipEvent_t)H->ev_fork,  (hipEvent_t)H->ev_big,
+              (hipEvent_t)H->ev_fork2,     (hipEvent_t)H->ev_join,  (hipEvent_t)H->ev_join2,
+              (hipEvent_t)H->ev_gfork,     (hipEvent_t)H->ev_gath};
 }
 
 }  // namespace
@@ -765,7 +768,7 @@ void mra_destroy(mra_plan_t P) {
     (void)hipStreamSynchronize((hipStream_t)P->side_stream);
     (void)hipStreamDestroy((hipStream_t)P->side_stream);
   }
-  for (void* ev : {P->ev_fork, P->ev_big, P->ev_fork2, P->ev_join, P->ev_join2})
+  for (void* ev : {P->ev_fork, P->ev_big, P->ev_fork2, P->ev_join, P->ev_join2, P->ev_gfork, P->ev_gath})
     if (ev) (void)hipEventDestroy((hipEvent_t)ev);
   if (P->graphs) {
     P->graphs->clear();

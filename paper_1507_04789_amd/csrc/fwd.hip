@@ -475,12 +475,31 @@ hipError_t launch_leaf_planes(const mra_plan_s& H, int c, const double* y, const
 // leaves proceed on `st`; side->big marks their completion and is awaited in
 // launch_forward_back.  With MRA_CHECKPOINT the leaf phase and the leaf
 // products run chunk by chunk here (no side stream).
+// plane M of every leaf row: the data (and trend columns) in leaf order
+static void launch_gather(const mra_plan_s& H, const double* y, int64_t y_stride, int nth, hipStream_t st,
+                          const double* X, int px) {
+  const DevPlan& P = H.dp;
+  int64_t gx = (P.npad * T + NT - 1) / NT;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, (int64_t)0, P.npad, X, px);
+}
+
 hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const double* theta, int nth, hipStream_t st,
                                 const Side* side, int64_t y_stride, const double* X, int px) {
   const DevPlan& P = H.dp;
   const PhaseFlops& F = H.pf;
   const int M = P.M;
   Runner run{P, nth, st, (H.cfg.flags & MRA_PLAIN) != 0, H.prof, H.tune};
+  // the data plane is first read by the leaf solves: with a second stream its
+  // gather runs there, beside the prior recursion's narrow top levels
+  const bool side_gather = side && H.nchunks == 1;
+  if (side_gather) {
+    hipError_t e;
+    if ((e = hipEventRecord(side->gfork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side->s, side->gfork, 0)) != hipSuccess) return e;
+    launch_gather(H, y, y_stride, nth, side->s, X, px);
+    if ((e = hipEventRecord(side->gath, side->s)) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_init, dim3(64, nth), dim3(NT), 0, st, P);
   for (int m = 0; m < M; ++m)
     run.tuned(F_PRIOR, MAP_IDENTITY, "prior", m, F.prior[m], 1, nullptr, k_prior, 0, H.nact_prior(m), theta, m);
@@ -498,9 +517,7 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
     }
     return hipGetLastError();
   }
-  int64_t gx = (P.npad * T + NT - 1) / NT;
-  if (gx > 4096) gx = 4096;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)gx, nth), dim3(NT), 0, st, P, y, y_stride, (int64_t)0, P.npad, X, px);
+  if (!side_gather) launch_gather(H, y, y_stride, nth, st, X, px);
   run.tuned(F_LEAF_ROWS, MAP_CHUNKED, "leaf_rows", -1, F.leaf_rows, 1, nullptr, k_leaf_rows, 0,
             (int64_t)H.row_tasks.size() / 2, theta);
   run.tuned(F_SIGMA, MAP_IDENTITY, "leaf_sigma", -1, F.sigma, 1, nullptr, k_sigma, 0, (int64_t)H.sig_tasks.size() / 3,
@@ -520,6 +537,10 @@ hipError_t launch_forward_front(const mra_plan_s& H, const double* y, const doub
   }
   run.tuned(F_POTRF, MAP_IDENTITY, "leaf_potrf", -1, F.potrf - H.potrf_flops_big(nbig), 1, nullptr, k_leaf_potrf, nbig,
             nfac);
+  if (side_gather) {
+    const hipError_t e = hipStreamWaitEvent(st, side->gath, 0);
+    if (e != hipSuccess) return e;
+  }
   run.tuned(F_TRSM, MAP_GROUPED, "leaf_trsm", -1, F.trsm - H.trsm_flops_big(nbig), M + 1, nullptr, k_leaf_trsm<false>,
             nbig * (M + 1), ntrsm, zcols(px));
   return hipGetLastError();

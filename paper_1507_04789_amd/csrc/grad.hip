@@ -560,11 +560,24 @@ __global__ __launch_bounds__(NT) void k_gsum(DevPlan P, const double* theta, dou
   const int th = blockIdx.x;
   double* S = slice(P, th);
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int64_t q = threadIdx.x; q < nslot; q += NT) {
-    const double* o = S + P.off_gpart + q * 4;
-    a += o[0];
-    b += o[1];
-    c += o[2];
+  // slots threadIdx.x, + NT, + 2 NT, ... in that order, eight loaded ahead
+  for (int64_t q0 = threadIdx.x; q0 < nslot; q0 += 8 * NT) {
+    double va[8], vb[8], vc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t q = q0 + (int64_t)u * NT;
+      const double* o = S + P.off_gpart + (q < nslot ? q : 0) * 4;
+      va[u] = o[0];
+      vb[u] = o[1];
+      vc[u] = o[2];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q0 + (int64_t)u * NT < nslot) {
+        a += va[u];
+        b += vb[u];
+        c += vc[u];
+      }
   }
   a = block_sum(a, red);
   b = block_sum(b, red);

@@ -180,6 +180,7 @@ hipError_t launch_forward(const mra_plan_s& H, const double* y, const double* th
 struct Side {
   hipStream_t s;
   hipEvent_t fork, big, fork2, join, join2;   // join: V done; join2: L^{-1} done
+  hipEvent_t gfork, gath;                     // the data gather, forked at the start of a call
 };
 // y_stride: parameter row b uses the data y + b * y_stride (0: the same data for all rows)
 // X (may be null): p trend columns [p][n] (caller's order) carried beside the

@@ -127,6 +127,8 @@ struct mra_plan_s {
   void* ev_fork2 = nullptr;      //   main -> side, reverse-pass leaf solves
   void* ev_join = nullptr;       //   side -> main, V = L^{-T} Y done
   void* ev_join2 = nullptr;      //   side -> main, L^{-1} done
+  void* ev_gfork = nullptr;      //   main -> side, the data gather at the start of a call
+  void* ev_gath = nullptr;       //   side -> main, data plane written
   int32_t last_nth = 1;
 };
 
