@@ -300,9 +300,10 @@ def summarize_engine(root: str):
            "  rocprofv3 --kernel-trace --stats --output-format csv -d %s/engine -o run -- "
            "./paper_1507_04789_amd/engine_probe" % root,
            "",
-           "probe output (HIP events over 10 launches after a warm-up; FP64 TFLOP/s of the tile products):"]
+           "probe output (tile variants: HIP events over 10 launches after a warm-up, FP64 TFLOP/s of the tile "
+           "products; MFMA peak: 5 launches; factorisation: in-kernel wall clock over 99 calls):"]
     for line in open(os.path.join(root, "engine.log")):
-        if re.match(r"^(library|A row|A k)", line):
+        if re.match(r"^(library|A row|A k|B transposed|MFMA peak|factorisation)", line):
             out.append("  " + line.rstrip())
     stats = None
     for dp, _, fs in os.walk(os.path.join(root, "engine")):
