@@ -23,6 +23,18 @@ __device__ __forceinline__ int64_t ancestor(const DevPlan& P, int m, int64_t i, 
   return i;
 }
 __device__ __forceinline__ int kl_index(int k, int l) { return k * (k + 1) / 2 + l; }
+// children of region (m-1, pidx) with observations below them, as a bit mask
+// (bit c: child c), and the region index of the c-th of them in child order
+__device__ __forceinline__ uint32_t active_children(const DevPlan& P, int m, int64_t pidx) {
+  uint32_t mask = 0;
+  for (int c = 0; c < P.Jl[m]; ++c)
+    if (P.slot_post[P.reg_base[m] + pidx * P.Jl[m] + c] >= 0) mask |= 1u << c;
+  return mask;
+}
+__device__ __forceinline__ int64_t nth_child(const DevPlan& P, int m, int64_t pidx, uint32_t mask, int c) {
+  for (; c > 0; --c) mask &= mask - 1;
+  return pidx * P.Jl[m] + __builtin_ctz(mask);
+}
 __device__ __forceinline__ int round16(int x) { return x <= 0 ? 0 : ((x + 15) & ~15); }
 __device__ __forceinline__ void kl_split(int kl, int& k, int& l) {
   k = 0;

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NT, 2) void k_post(DevPlan P, int m, double* out_lo
 
 // child sums for level m-1 (eq. mainquantities with eq. helpquantities):
 //   A^{k,l}_P = sum_c (A^{k,l}_c - Z^k_c' Z^l_c),  w^k_P = sum_c (w^k_c - Z^k_c' z_c)
-__global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_post_reduce(DevPlan P, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -327,15 +327,13 @@ __global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap
   double* S = slice(P, th);
   Post pp = post_of(P, S, m - 1, pidx);
   // children with observations below them (the others contribute zero)
-  int64_t ch[16];
-  int nch = 0;
-  for (int c = 0; c < P.Jl[m]; ++c)
-    if (post_active(P, m, pidx * P.Jl[m] + c)) ch[nch++] = pidx * P.Jl[m] + c;
+  const uint32_t cm = active_children(P, m, pidx);
+  const int nch = __builtin_popcount(cm);
   Acc acc;
   acc_zero(acc);
-  for (int c = 0; c < nch; ++c) acc_load(acc, post_of(P, S, m, ch[c]).A(k, l), T, true);
+  for (int c = 0; c < nch; ++c) acc_load(acc, post_of(P, S, m, nth_child(P, m, pidx, cm, c)).A(k, l), T, true);
   gemm_segs2(acc, nch, [&](int c) {
-    Post pc = post_of(P, S, m, ch[c]);
+    Post pc = post_of(P, S, m, nth_child(P, m, pidx, cm, c));
     return seg<Op::T, Op::N>(pc.Z(k), T, pc.Z(l), T, -1.0);
   }, lds);
   acc_store(acc, pp.A(k, l), T);
@@ -343,7 +341,7 @@ __global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap
     double w = 0.0;
     const int col = threadIdx.x & 63;
     for (int c = 0; c < nch; ++c) {
-      Post pc = post_of(P, S, m, ch[c]);
+      Post pc = post_of(P, S, m, nth_child(P, m, pidx, cm, c));
       const double* Zk = pc.Z(k);
       const double* zw = pc.zw();
       double zk[T / 4], zv[T / 4];   // rows wave, wave + 4, ...: all loads issued first
@@ -359,22 +357,23 @@ __global__ __launch_bounds__(NT, 3) void k_post_reduce(DevPlan P, int m, TaskMap
     w = wave_col_sum(w, lds);
     if (threadIdx.x < T) pp.omega(k)[threadIdx.x] = w;
   }
-  if (kl == 0 && threadIdx.x == 0) {
-    double dv[16], uv[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < nch) {
-        Post pc = post_of(P, S, m, ch[c]);
-        dv[c] = *pc.d();
-        uv[c] = *pc.u();
-      }
-    double dsum = 0.0, usum = 0.0;
-    for (int c = 0; c < nch; ++c) {
-      dsum += dv[c];
-      usum += uv[c];
+  if (kl == 0 && wave_id() == 0) {   // lane c loads child c's d and u; summed in child order
+    const int c = lane_id();
+    double dv = 0.0, uv = 0.0;
+    if (c < nch) {
+      Post pc = post_of(P, S, m, nth_child(P, m, pidx, cm, c));
+      dv = *pc.d();
+      uv = *pc.u();
     }
-    *pp.d() = dsum;
-    *pp.u() = usum;
+    double dsum = 0.0, usum = 0.0;
+    for (int q = 0; q < nch; ++q) {
+      dsum += readlane_d(dv, q);
+      usum += readlane_d(uv, q);
+    }
+    if (c == 0) {
+      *pp.d() = dsum;
+      *pp.u() = usum;
+    }
   }
 }
 

@@ -529,7 +529,7 @@ __global__ __launch_bounds__(NT, 2) void k_rprior(DevPlan P, const double* theta
 
 // Tsum of a level-(m-1) region: sum over children (level m) of
 // Tsum_c^{l,k} + Wbar_c^l' W^^k_c, k <= l <= m-1
-__global__ __launch_bounds__(NT, 3) void k_rT(DevPlan P, int m, TaskMap tm) {
+__global__ __launch_bounds__(NT, 4) void k_rT(DevPlan P, int m, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
   __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
@@ -540,16 +540,14 @@ __global__ __launch_bounds__(NT, 3) void k_rT(DevPlan P, int m, TaskMap tm) {
   int l, k;
   kl_split((int)(gid % nkl), l, k);
   double* S = slice(P, th);
-  int64_t ch[16];      // children with observations below them
-  int nch = 0;
-  for (int c = 0; c < P.Jl[m]; ++c)
-    if (post_active(P, m, pidx * P.Jl[m] + c)) ch[nch++] = pidx * P.Jl[m] + c;
+  const uint32_t cm = active_children(P, m, pidx);   // children with observations below them
+  const int nch = __builtin_popcount(cm);
   Acc acc;
   acc_zero(acc);
-  for (int cc = 0; cc < nch; ++cc) acc_load(acc, grad_of(P, S, m, ch[cc]).Tsum(l, k), T, true);
+  for (int cc = 0; cc < nch; ++cc) acc_load(acc, grad_of(P, S, m, nth_child(P, m, pidx, cm, cc)).Tsum(l, k), T, true);
   gemm_segs2(acc, nch, [&](int cc) {
-    return seg<Op::T, Op::N>(grad_of(P, S, m, ch[cc]).Wbar(l), T, prior_reg(P, S, m, ch[cc]) + (int64_t)k * TT, T,
-                             1.0);
+    const int64_t ch = nth_child(P, m, pidx, cm, cc);
+    return seg<Op::T, Op::N>(grad_of(P, S, m, ch).Wbar(l), T, prior_reg(P, S, m, ch) + (int64_t)k * TT, T, 1.0);
   }, lds);
   acc_store(acc, grad_of(P, S, m - 1, pidx).Tsum(l, k), T);
 }
