@@ -269,11 +269,16 @@ def summarize_profiles(root: str, copy_bytes: int):
 
 def _timeline(path: str, step: int = 2):
     """Launch timeline of one step of the traced run: every kernel's start
-    and end relative to the step's first launch, with its hardware queue.
+    and end relative to the step's first launch, with its hardware queue
+    (kernels in order of their start times, a step from one call's first
+    kernel to the next call's).
     Step 2 of a `--steps 3 --warmup 1` run is the second timed graph replay
     (step 0 is the warm-up, steps 4..6 the eager profiled pass)."""
-    rows = [r for r in _csv(path) if "mra::k_" in r["Kernel_Name"]]
-    starts = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "init"]
+    rows = sorted((r for r in _csv(path) if "mra::k_" in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+    # a gradient call starts by clearing its partial sums, a log-likelihood call with init
+    names = [_short(r["Kernel_Name"]) for r in rows]
+    marker = "zero_gpart" if "zero_gpart" in names else "init"
+    starts = [i for i, nm in enumerate(names) if nm == marker]
     if len(starts) <= step:
         return []
     a = starts[step]
