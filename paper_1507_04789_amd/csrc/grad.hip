@@ -145,11 +145,14 @@ __global__ __launch_bounds__(NT, 4) void k_rpost(DevPlan P, int m, TaskMap tm) {
 }
 
 // ---------------------------------------------------------------- leaves
-// V = L_Sigma^{-T} Y for one column plane (backward substitution by tiles)
+// V = L_Sigma^{-T} Y for one column plane (backward substitution by tiles).
+// After the updates the right-hand side tile stays in LDS for the product
+// with the diagonal inverse instead of a round trip through global memory
+// (same products in the same order).
 __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   const int th = blockIdx.y;
   const int32_t* task = P.trsm_tasks + 2 * tk0;
   const int leaf = task[0], cpl = task[1];
@@ -167,19 +170,21 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
   Acc acc;
   for (int ib = nb - 1; ib >= 0; --ib) {
     const int mr = round16(min(T, nR - T * ib));
-    const double* R = Y + (int64_t)ib * TT;   // right-hand side after the updates
-    if (ib < nb - 1) {
+    const double* R = Y + (int64_t)ib * TT;   // right-hand side
+    if (ib < nb - 1) {                         // updated by the tiles below, then kept in LDS
       acc_load(acc, R, T);
       gemm_segs2(acc, nb - 1 - ib, [&](int q) {
         const int jb = ib + 1 + q;
         return seg<Op::T, Op::N>(base + ((int64_t)jb * nb + ib) * TT, T, V + (int64_t)jb * TT, T, -1.0);
       }, lds, mr, nc);
-      acc_store(acc, V + (int64_t)ib * TT, T);
+      acc_to_lds(acc, lds);
       __syncthreads();
-      R = V + (int64_t)ib * TT;
+      acc_zero(acc);
+      gemm_lds_b(acc, dinv + (int64_t)ib * TT, T, true, lds, 1.0, lds + LDS_DOUBLES, mr, nc);
+    } else {
+      acc_zero(acc);
+      gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr, nc);
     }
-    acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::T, Op::N>(dinv + (int64_t)ib * TT, T, R, T, 1.0); }, lds, mr, nc);
     acc_store(acc, V + (int64_t)ib * TT, T);
     __syncthreads();
   }
@@ -187,11 +192,13 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_v(DevPlan P, TaskMap tm) {
 
 // tile column j < nb - 1 of L_Sigma^{-1} below the diagonal (forward
 // substitution of the identity); the diagonal tiles are the inverses the
-// factorisation keeps, read in place
-__global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
+// factorisation keeps, read in place.  Each new tile stays in LDS for its
+// product with the diagonal inverse (same products in the same order as a
+// store and reload).
+__global__ __launch_bounds__(NT, 3) void k_rleaf_linv(DevPlan P, TaskMap tm) {
   const int64_t tk0 = task_of(tm);
   if (tk0 < 0) return;
-  __shared__ __attribute__((aligned(32))) double lds[LDS_DOUBLES];
+  __shared__ __attribute__((aligned(32))) double lds[LDS_SWEEP];
   const int th = blockIdx.y;
   const int32_t* task = P.linv_tasks + 2 * tk0;
   const int leaf = task[0], j = task[1];
@@ -209,12 +216,11 @@ __global__ __launch_bounds__(NT, 4) void k_rleaf_linv(DevPlan P, TaskMap tm) {
       const double* Xkj = kb == j ? dinv + (int64_t)j * TT : Li + ((int64_t)kb * nb + j) * TT;
       return seg<Op::N, Op::N>(base + ((int64_t)ib * nb + kb) * TT, T, Xkj, T, -1.0);
     }, lds);
-    double* out = Li + ((int64_t)ib * nb + j) * TT;
-    acc_store(acc, out, T);
+    acc_to_lds(acc, lds);
     __syncthreads();
     acc_zero(acc);
-    gemm_segs(acc, 1, [&](int) { return seg<Op::N, Op::N>(dinv + (int64_t)ib * TT, T, out, T, 1.0); }, lds);
-    acc_store(acc, out, T);
+    gemm_lds_b(acc, dinv + (int64_t)ib * TT, T, false, lds, 1.0, lds + LDS_DOUBLES);
+    acc_store(acc, Li + ((int64_t)ib * nb + j) * TT, T);
     __syncthreads();
   }
 }
